@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark: LMA fit + predict on one MI355X at n = 524288.
+
+Workload (the n=524288 configuration): d = 21 inputs from a mixture of 32
+Gaussians, M = 256 capacity-bounded k-means blocks (1024..3072 points),
+Markov order B = 3, |S| = 1024, 65536 test points.  One step = lma_fit
+(summaries, global solve, LML) + lma_predict (mean and variance) on inputs
+already resident in HBM.
+
+Prints one JSON line.  `value` is the float64 fit+predict time per step
+(seconds, lower is better); the mixed-precision time, its speedup and its
+error against the float64 path, the LML evaluation rate, the roofline of the
+dominant kernel (measured live with HIP events) and a CPU-oracle baseline on
+a bounded sample are reported beside it.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "mixed": 157.3e12}   # dense MFMA: float64, float32
+METRIC = "LMA fit+predict s and LML+grad evals/s at n=512K; mixed vs FP64 at stated err"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def window_sizes(p):
+    M, B, bp = p.M, min(p.B, p.M - 1), p.block_ptr
+    J, w = [], []
+    for m in range(M):
+        hi = min(m + B, M - 1)
+        ww = int(bp[hi + 1] - bp[m + 1]) if hi > m else 0
+        w.append(ww)
+        J.append(ww + int(bp[m + 1] - bp[m]))
+    return np.array(J, dtype=np.float64), np.array(w, dtype=np.float64)
+
+
+def algorithmic_flops(p):
+    """Whole-path algorithmic flops: Sigma_SS Cholesky and V, unique band-pair
+    residual assembly, window Cholesky, window solves with the s+1 right-hand
+    sides, and the prediction solves of each test point against the windows of
+    its block (plus the low-rank terms)."""
+    s, n, M, B = p.s, p.n, p.M, min(p.B, p.M - 1)
+    b = np.diff(p.block_ptr).astype(np.float64)
+    u = np.diff(p.u_block_ptr).astype(np.float64)
+    J, w = window_sizes(p)
+    band = sum(b[m] * b[k] for m in range(M) for k in range(m, min(m + B, M - 1) + 1))
+    f_fit = 2 * s ** 3 / 3 + 2 * n * s ** 2 + 2 * s * band + np.sum(J ** 3) / 3 + np.sum(J ** 2) * (s + 1)
+    f_pred = p.n_u * s ** 2 + 5 * p.n_u * s ** 2
+    for q in range(M):
+        if u[q] == 0:
+            continue
+        lo = max(0, q - B)
+        Nq = b[max(0, q - B):min(M, q + B + 1)].sum()
+        f_pred += 2 * s * u[q] * Nq + u[q] * np.sum(J[lo:q + 1] ** 2)
+    return float(f_fit), float(f_pred)
+
+
+def cpu_baseline(p, budget_s=25.0):
+    """The oracle timed on a bounded sample: support part (L_SS, V over all of
+    D and U) plus a spread of windows, scaled to all M windows by their cubic
+    cost model."""
+    from oracle import lma as olma
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    J, _ = window_sizes(p)
+    u = np.diff(p.u_block_ptr).astype(np.float64)
+    cost = J ** 3 / 3 + J ** 2 * (2 * p.s + 1) + np.array(
+        [J[m] ** 2 * u[m:min(m + p.B, p.M - 1) + 1].sum() for m in range(p.M)])
+    t0 = time.perf_counter()
+    f = olma.Fit(p, windows=[], test=True)
+    t_setup = time.perf_counter() - t0
+    order = np.argsort(J)
+    picks = list(order[np.linspace(0, p.M - 1, 16).astype(int)])
+    done, t_win = [], 0.0
+    for m in picks:
+        t1 = time.perf_counter()
+        f.window(int(m))
+        t_win += time.perf_counter() - t1
+        done.append(int(m))
+        if t_setup + t_win > budget_s:
+            break
+    t1 = time.perf_counter()
+    f.finish()
+    f.predict()
+    t_fin = time.perf_counter() - t1
+    est = t_setup + t_fin + t_win * cost.sum() / cost[done].sum()
+    return {"value": est, "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": f"float64 oracle (whitened windows): support factorisation and V for all "
+                      f"{p.n} + {p.n_u} points, then {len(done)} of {p.M} windows with their test "
+                      f"right-hand sides ({t_win:.1f} s), scaled to all windows by "
+                      f"J^3/3 + J^2 (2|S|+1+u) cost; measured {t_setup + t_win + t_fin:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--modes", default="fp64,mixed")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--small", action="store_true", help="n=65536 workload (quick check)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding design); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1411_4510_amd as lma
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    lma.load()
+    t0 = time.perf_counter()
+    p = synth.make_config(1) if args.small else synth.make_config(2)
+    log(f"inputs drawn in {time.perf_counter() - t0:.1f} s: n={p.n} d={p.d} M={p.M} B={p.B} s={p.s} n_u={p.n_u}")
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    X, y, S, U = dev(p.X), dev(p.y), dev(p.S), dev(p.U)
+    torch.cuda.synchronize()
+
+    def step(prec):
+        st = lma.fit(X, y, p.block_ptr, S, p.B, p.log_hyp, p.prior_mean, precision=prec)
+        t_fit = time.perf_counter()
+        mean, var = st.predict(U, p.u_block_ptr)
+        lml_val = st.lml()
+        st.free()
+        return mean, var, lml_val, t_fit
+
+    res, outs = {}, {}
+    for prec in [m for m in args.modes.split(",") if m]:
+        for i in range(args.warmup):
+            step(prec)
+            log(f"{prec} warmup {i} done")
+        lma.profile_enable(True)
+        lma.profile_read(reset=True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        fit_s = 0.0
+        for i in range(args.steps):
+            ts = time.perf_counter()
+            mean, var, lml_val, t_fit = step(prec)
+            fit_s += t_fit - ts
+            log(f"{prec} step {i} done")
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t_start) / args.steps
+        prof = lma.profile_read(reset=True)
+        lma.profile_enable(False)
+        outs[prec] = (mean.cpu().numpy(), var.cpu().numpy(), lml_val)
+        res[prec] = {"s_per_step": dt, "fit_s": fit_s / args.steps, "predict_s": dt - fit_s / args.steps,
+                     "lml": lml_val, "profile": prof}
+        log(f"{prec}: {dt:.3f} s/step, profile {prof}")
+
+    # LML evaluations per second (forward) in float64 at this shape
+    lml_rate = None
+    if "fp64" in res:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        lma.lml(X, y, p.block_ptr, S, p.B, p.log_hyp, p.prior_mean, precision="fp64")
+        torch.cuda.synchronize()
+        lml_rate = 1.0 / (time.perf_counter() - t1)
+
+    f_fit, f_pred = algorithmic_flops(p)
+    head = "fp64" if "fp64" in res else list(res)[0]
+    prof = res[head]["profile"]
+    achieved = prof["update_alg_flops"] / (prof["update_ms"] * 1e-3) if prof["update_ms"] > 0 else 0.0
+    roofline = {"bound": "mfma", "kernel": f"k_update<{'double' if head == 'fp64' else 'float'}>",
+                "achieved": achieved / 1e12, "peak": PEAK[head] / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / PEAK[head], "traffic": None,
+                "path_alg_tflops": (f_fit + f_pred) / res[head]["s_per_step"] / 1e12,
+                "path_frac": (f_fit + f_pred) / res[head]["s_per_step"] / PEAK[head],
+                "update_share_of_step": prof["update_ms"] * 1e-3 / args.steps / res[head]["s_per_step"]}
+    out = {
+        "metric": METRIC,
+        "value": res[head]["s_per_step"],
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res[head]["s_per_step"] * 1e3,
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"LMA fit+predict (mean+variance), n={p.n}, d={p.d}, M={p.M} k-means blocks "
+                               f"({int(np.diff(p.block_ptr).min())}..{int(np.diff(p.block_ptr).max())}), "
+                               f"B={p.B}, |S|={p.s}, n_u={p.n_u}",
+                   "n": p.n, "d": p.d, "M": p.M, "B": p.B, "s": p.s, "n_u": p.n_u},
+        "fp64": res.get("fp64"),
+        "mixed": res.get("mixed"),
+        "lml_evals_per_s_fp64": lml_rate,
+        "alg_flops": {"fit": f_fit, "predict": f_pred},
+        "roofline": roofline,
+    }
+    if "fp64" in outs and "mixed" in outs:
+        a, b = outs["mixed"], outs["fp64"]
+        r = lambda x, y_: float(np.linalg.norm(x - y_) / np.linalg.norm(y_))
+        out["mixed"]["speedup_vs_fp64"] = res["fp64"]["s_per_step"] / res["mixed"]["s_per_step"]
+        out["mixed"]["rel_err_vs_fp64"] = {"mean": r(a[0], b[0]), "var": r(a[1], b[1]),
+                                           "lml": abs(a[2] - b[2]) / abs(b[2])}
+    if "fp64" in outs and p.y_u is not None:
+        out["rmse_fp64"] = float(np.sqrt(np.mean((outs["fp64"][0] - p.y_u) ** 2)))
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(p, budget_s=args.cpu_budget)
+        log(f"cpu baseline {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+"""Python binding of the MI355X LMA library (liblma.so, C ABI in include/lma.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of liblma.so.  PyTorch supplies device memory and the current HIP stream.
+There is no CPU fallback: if the library is missing, load() raises.
+
+    import paper_1411_4510_amd as lma
+    st = lma.fit(X, y, block_ptr, S, B, log_hyp, prior_mean=0.0, precision="fp64")
+    mean, var = st.predict(U, u_block_ptr)
+    val = lma.lml(X, y, block_ptr, S, B, log_hyp)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblma.so")
+
+LMA_OK, LMA_E_ARG, LMA_E_NOT_PD, LMA_E_HIP, LMA_E_NOMEM = 0, 1, 2, 3, 4
+PRECISION = {"fp64": 0, "mixed": 1}
+EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml",
+           "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
+           "lma_profile_read")
+
+
+class LmaError(RuntimeError):
+    def __init__(self, status, message, block=None):
+        super().__init__(f"[{status}] {message}" + (f" (block {block})" if block is not None else ""))
+        self.status = status
+        self.block = block
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("d", ctypes.c_int64), ("s", ctypes.c_int64),
+        ("M", ctypes.c_int64), ("B", ctypes.c_int64),
+        ("X", ctypes.c_void_p), ("y", ctypes.c_void_p),
+        ("block_ptr", ctypes.POINTER(ctypes.c_int64)),
+        ("S", ctypes.c_void_p),
+        ("log_hyp", ctypes.POINTER(ctypes.c_double)),
+        ("prior_mean", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("mem_budget_bytes", ctypes.c_int64),
+    ]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [
+        ("update_ms", ctypes.c_double), ("diag_ms", ctypes.c_double),
+        ("trsm_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
+        ("update_alg_flops", ctypes.c_double),
+        ("update_launches", ctypes.c_int64), ("other_launches", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblma.so (built in-tree by build()); raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first (paper_1411_4510_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    lib.lma_fit.argtypes = [ctypes.POINTER(_Problem), vp, ctypes.POINTER(vp)]
+    lib.lma_fit.restype = st
+    lib.lma_predict.argtypes = [vp, i64, vp, ctypes.POINTER(i64), vp, vp, vp]
+    lib.lma_predict.restype = st
+    lib.lma_lml.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_double),
+                            ctypes.POINTER(ctypes.c_double), vp]
+    lib.lma_lml.restype = st
+    lib.lma_free.argtypes = [vp]
+    lib.lma_free.restype = None
+    lib.lma_state_lml.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    lib.lma_state_lml.restype = st
+    lib.lma_last_error.restype = ctypes.c_char_p
+    lib.lma_failed_block.restype = i64
+    lib.lma_version.restype = ctypes.c_char_p
+    lib.lma_profile_enable.argtypes = [ctypes.c_int]
+    lib.lma_profile_enable.restype = None
+    lib.lma_profile_read.argtypes = [ctypes.POINTER(Profile), ctypes.c_int]
+    lib.lma_profile_read.restype = st
+    _lib = lib
+    return lib
+
+
+def _check(status):
+    if status != LMA_OK:
+        msg = _lib.lma_last_error().decode()
+        block = int(_lib.lma_failed_block()) if status == LMA_E_NOT_PD else None
+        raise LmaError(status, msg, block)
+
+
+def _dev(a, torch, dtype=None):
+    """Device float64 contiguous tensor from a numpy array or tensor."""
+    dtype = dtype or torch.float64
+    if isinstance(a, torch.Tensor):
+        t = a.to(device="cuda", dtype=dtype)
+    else:
+        t = torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+    return t.contiguous()
+
+
+def _stream(torch, stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class _Inputs:
+    """Keeps device copies and host arrays alive for the duration of a call."""
+
+    def __init__(self, X, y, block_ptr, S, B, log_hyp, prior_mean, precision, mem_budget):
+        import torch
+        self.X = _dev(X, torch)
+        self.y = _dev(y, torch).reshape(-1)
+        self.S = _dev(S, torch)
+        self.bp = np.ascontiguousarray(np.asarray(block_ptr, dtype=np.int64))
+        self.lh = np.ascontiguousarray(np.asarray(log_hyp, dtype=np.float64))
+        n, d = self.X.shape
+        pr = _Problem()
+        pr.n, pr.d, pr.s = n, d, self.S.shape[0]
+        pr.M, pr.B = len(self.bp) - 1, int(B)
+        pr.X, pr.y, pr.S = self.X.data_ptr(), self.y.data_ptr(), self.S.data_ptr()
+        pr.block_ptr = self.bp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        pr.log_hyp = self.lh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        pr.prior_mean = float(prior_mean)
+        pr.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        pr.reserved = 0
+        pr.mem_budget_bytes = int(mem_budget)
+        self.problem = pr
+
+
+class State:
+    """A fitted LMA model (owns an lma_state)."""
+
+    def __init__(self, handle, M):
+        self._h = handle
+        self.M = M
+
+    def predict(self, U, u_block_ptr, want_var=True, stream=None):
+        """Predictive mean and variance (device float64 tensors)."""
+        import torch
+        Ud = _dev(U, torch)
+        ubp = np.ascontiguousarray(np.asarray(u_block_ptr, dtype=np.int64))
+        n_u = Ud.shape[0]
+        mean = torch.empty(n_u, dtype=torch.float64, device="cuda")
+        var = torch.empty(n_u, dtype=torch.float64, device="cuda") if want_var else None
+        _check(_lib.lma_predict(self._h, n_u, ctypes.c_void_p(Ud.data_ptr()),
+                                ubp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                ctypes.c_void_p(mean.data_ptr()),
+                                ctypes.c_void_p(var.data_ptr()) if var is not None else None,
+                                _stream(torch, stream)))
+        return mean, var
+
+    def lml(self):
+        out = ctypes.c_double()
+        _check(_lib.lma_state_lml(self._h, ctypes.byref(out)))
+        return out.value
+
+    def free(self):
+        if self._h:
+            _lib.lma_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fit(X, y, block_ptr, S, B, log_hyp, prior_mean=0.0, precision="fp64", mem_budget=0, stream=None):
+    """lma_fit: local and global summaries of the LMA model (Definitions 1-2)."""
+    import torch
+    load()
+    inp = _Inputs(X, y, block_ptr, S, B, log_hyp, prior_mean, precision, mem_budget)
+    h = ctypes.c_void_p()
+    _check(_lib.lma_fit(ctypes.byref(inp.problem), _stream(torch, stream), ctypes.byref(h)))
+    return State(h, inp.problem.M)
+
+
+def lml(X, y, block_ptr, S, B, log_hyp, prior_mean=0.0, precision="fp64", grad=False, stream=None):
+    """lma_lml: log marginal likelihood (and its gradient in log_hyp)."""
+    import torch
+    load()
+    inp = _Inputs(X, y, block_ptr, S, B, log_hyp, prior_mean, precision, 0)
+    out = ctypes.c_double()
+    g = np.zeros(inp.problem.d + 2) if grad else None
+    _check(_lib.lma_lml(ctypes.byref(inp.problem), ctypes.byref(out),
+                        g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if grad else None,
+                        _stream(torch, stream)))
+    return (out.value, g) if grad else out.value
+
+
+def fit_problem(p, precision="fp64", **kw):
+    """fit() for a synthetic Problem object (X, y, block_ptr, S, B, log_hyp, prior_mean)."""
+    return fit(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, precision=precision, **kw)
+
+
+def profile_enable(on=True):
+    """Bracket every library kernel launch with HIP events (live timing)."""
+    load()
+    _lib.lma_profile_enable(1 if on else 0)
+
+
+def profile_read(reset=True):
+    load()
+    out = Profile()
+    _check(_lib.lma_profile_read(ctypes.byref(out), 1 if reset else 0))
+    return out.as_dict()
+
+
+def version():
+    load()
+    return _lib.lma_version().decode()

@@ -1,0 +1,107 @@
+// Tiled left-looking Cholesky / triangular-solve engine for gfx950.
+//
+// A "problem" is a symmetric positive-definite matrix given tile by tile
+// (the J rows) plus right-hand-side rows (RHS rows) that are solved against
+// its Cholesky factor on the fly: for RHS rows b the engine produces
+// b L^-T, i.e. rows of (L^-1 b^T)^T.  Every entry of the matrix and of the
+// right-hand sides is generated inside the update kernel (covariance tile,
+// explicit matrix, or the centred output vector) and corrected by
+//
+//   C_ij = K_ij - V_i V_j^T - sum_{k<j} L_ik L_jk^T
+//
+// where V rows are the whitened support rows V^T = K_XS L_SS^-T of the
+// points of the tile (present only when both tiles carry them).  The V term
+// turns the covariance into the residual R = Sigma - Q of the paper, so the
+// residual matrix is never stored.
+//
+// All problems of one run advance column by column in lock step: for column
+// tile j one update launch covers every row tile i >= j of every problem
+// (and every RHS row tile), one launch factors the diagonal tiles and
+// inverts them, and one launch applies the inverse to the tiles below.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lma {
+
+constexpr int TB = 128;     // tile edge
+constexpr int NT = 256;     // threads per workgroup (4 wave64)
+constexpr int DIAG_LD = TB + 1;
+
+enum Src : int32_t { SRC_KERNEL = 0, SRC_EXPLICIT = 1, SRC_CVEC = 2 };
+
+template <typename T>
+struct RowTile {
+  T* panel;          // row r of this row tile at panel + r*ld; column tile k at +k*TB
+  int64_t ld;
+  const T* vt;       // whitened support rows of the tile's points (row r at vt + r*vld) or null
+  const T* xs;       // length-scaled coordinates of the tile's points ([r][d]) or null
+  const T* cv;       // centred outputs y - mu of the tile's points (column side of SRC_CVEC)
+  const T* expl;     // explicit entries: row r, global column c at expl[r*eld + c]
+  int64_t eld;
+  int32_t nvalid;    // rows that are real points / real entries
+  int32_t nstore;    // rows physically stored (loads beyond read 0, stores skipped)
+  int32_t src;       // Src
+  int32_t is_j;      // 1 for rows of the matrix being factored
+};
+
+struct ProbDesc {
+  int32_t T;            // number of column tiles (J row tiles)
+  int32_t R;            // number of RHS row tiles
+  int32_t first;        // index of its first RowTile (J tiles, then RHS tiles)
+  int32_t ld_from;      // first column tile whose log-diagonal counts toward the log-det
+  int64_t invdiag_off;  // element offset of its inverted diagonal tiles [T][TB][TB]
+};
+
+struct WorkItem {
+  int32_t p;
+  int32_t tile;   // local row-tile index: 0..T-1 J tiles, T..T+R-1 RHS tiles
+};
+
+template <typename T>
+struct StepArgs {
+  const RowTile<T>* rt;
+  const ProbDesc* pd;
+  const WorkItem* items;
+  int32_t nitems;
+  int32_t j;          // column tile of this step
+  int32_t vlen;       // length of the whitened support rows (multiple of 16)
+  int32_t d;
+  int64_t vld;
+  double sf2, sn2;
+  T* invdiag;
+  double* logdiag;    // [problem][maxT]
+  int32_t* status;    // [problem], set to 1 when a pivot is not positive
+  int32_t maxT;
+};
+
+// Host-side launchers (engine.hip).
+template <typename T>
+void launch_update(const StepArgs<T>& a, hipStream_t st);
+template <typename T>
+void launch_diag(const StepArgs<T>& a, const int32_t* plist, int np, hipStream_t st);
+template <typename T>
+void launch_trsm(const StepArgs<T>& a, hipStream_t st);
+
+// Batched float64-accumulating GEMM over tiles: item i computes
+//   acc = sum over its terms t of A_t[:, k0:k1] B_t[:, k0:k1]^T   (128 x 128)
+// and writes (or adds) acc into its output tile.  A_t and B_t rows are
+// contiguous in k; rows past anr / bnr read as zero.  Used for the global
+// summary (sum over windows of Z^T Z, Z^T z, z^T z) and for the per-test-point
+// prediction sums.
+template <typename T>
+struct GemmTerm {
+  const T* a; int64_t lda; int32_t anr;
+  const T* b; int64_t ldb; int32_t bnr;
+  int32_t k0, k1;        // column range (multiples of 16)
+};
+struct GemmOut {
+  double* out; int64_t ld;
+  int32_t rows, cols;    // valid rows / columns of the output tile
+  int32_t accumulate;    // 1: add to the output, 0: overwrite
+  int32_t t0, t1;        // terms [t0, t1)
+};
+template <typename T>
+void launch_tile_gemm(const GemmTerm<T>* terms, const GemmOut* outs, int nout, hipStream_t st);
+
+}  // namespace lma

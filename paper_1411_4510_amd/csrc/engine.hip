@@ -1,0 +1,408 @@
+// Device kernels of the tiled Cholesky / triangular-solve engine (gfx950).
+//
+// Work decomposition: a workgroup of 4 wave64 computes one 128x128 output
+// tile; wave (wr, wc) owns the 64x64 quadrant (wr, wc) as 4x4 MFMA 16x16
+// sub-tiles.  Operand fragments are read straight from HBM/L2 in the MFMA
+// 16x16x4 input layout (lane l supplies row l%16 and four consecutive k
+// values starting at 4*(l/16)); the four MFMA k-steps of a 16-wide k chunk
+// consume those four values, so each lane issues one contiguous 4-element
+// load per sub-tile row per chunk and the next chunk is prefetched while the
+// current one runs on the matrix cores.
+#include "engine.h"
+
+namespace lma {
+
+typedef double dv4 __attribute__((ext_vector_type(4)));
+typedef float fv4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct V4;
+template <>
+struct V4<double> { typedef dv4 type; };
+template <>
+struct V4<float> { typedef fv4 type; };
+
+template <typename Tc>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef dv4 acc;
+  __device__ static inline acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // register v of lane l holds row (l/16) + 4v, column l%16 of the 16x16 tile
+  __device__ static inline int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+template <>
+struct Mfma<float> {
+  typedef fv4 acc;
+  __device__ static inline acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // register v of lane l holds row 4*(l/16) + v, column l%16 of the 16x16 tile
+  __device__ static inline int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+
+__device__ inline double k_exp(double x) { return exp(x); }
+__device__ inline float k_exp(float x) { return expf(x); }
+__device__ inline double k_sqrt(double x) { return sqrt(x); }
+__device__ inline float k_sqrt(float x) { return sqrtf(x); }
+
+// Workgroups are dealt round-robin to the 8 XCDs; remap so that consecutive
+// work items (tiles of the same problem, which share the B operand) land on
+// the same XCD and its L2.  The grid is padded to a multiple of 8.
+__device__ inline int xcd_logical(int bid, int nb) {
+  const int per = nb >> 3;
+  return (bid & 7) * per + (bid >> 3);
+}
+
+// acc[ra][rb] += A[arow0 + 16 ra + i, k] * Bm[brow0 + 16 rb + j, k] over k in [k0, k1).
+template <typename Tin, typename Tc>
+__device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
+                                          const Tin* __restrict__ A, int64_t lda, int anr,
+                                          const Tin* __restrict__ Bm, int64_t ldb, int bnr,
+                                          int k0, int k1, int arow0, int brow0, int lane) {
+  typedef typename V4<Tin>::type vin;
+  const int r16 = lane & 15, kq = (lane >> 4) << 2;
+  const Tin* pa[4];
+  const Tin* pb[4];
+  bool va[4], vb[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int ra = arow0 + t * 16 + r16;
+    va[t] = ra < anr;
+    pa[t] = A + (int64_t)(va[t] ? ra : 0) * lda + k0 + kq;
+    const int rb = brow0 + t * 16 + r16;
+    vb[t] = rb < bnr;
+    pb[t] = Bm + (int64_t)(vb[t] ? rb : 0) * ldb + k0 + kq;
+  }
+  const int nc = (k1 - k0) >> 4;
+  if (nc <= 0) return;
+  vin ca[4], cb[4], na[4], nb[4];
+  const vin zero = {Tin(0), Tin(0), Tin(0), Tin(0)};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    ca[t] = va[t] ? *(const vin*)(pa[t]) : zero;
+    cb[t] = vb[t] ? *(const vin*)(pb[t]) : zero;
+  }
+  for (int c = 0; c < nc; ++c) {
+    const bool more = c + 1 < nc;
+    if (more) {
+      const int off = (c + 1) << 4;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        na[t] = va[t] ? *(const vin*)(pa[t] + off) : zero;
+        nb[t] = vb[t] ? *(const vin*)(pb[t] + off) : zero;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+      for (int ra = 0; ra < 4; ++ra) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          acc[ra][rb] = Mfma<Tc>::op((Tc)ca[ra][e], (Tc)cb[rb][e], acc[ra][rb]);
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        ca[t] = na[t];
+        cb[t] = nb[t];
+      }
+    }
+  }
+}
+
+template <typename Tc>
+__device__ inline void zero_acc(typename Mfma<Tc>::acc (&acc)[4][4]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = (typename Mfma<Tc>::acc){Tc(0), Tc(0), Tc(0), Tc(0)};
+}
+
+// ---------------------------------------------------------------------------
+// update: C_ij = K_ij - V_i V_j^T - sum_{k<j} L_ik L_jk^T for every item (p, i)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  if (logical >= a.nitems) return;
+  const WorkItem it = a.items[logical];
+  const ProbDesc pd = a.pd[it.p];
+  const RowTile<T> ri = a.rt[pd.first + it.tile];
+  const RowTile<T> rj = a.rt[pd.first + a.j];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+
+  typename Mfma<T>::acc acc[4][4];
+  zero_acc<T>(acc);
+  if (ri.vt != nullptr && rj.vt != nullptr && a.vlen > 0)
+    wave_gemm<T, T>(acc, ri.vt, a.vld, ri.nvalid, rj.vt, a.vld, rj.nvalid, 0, a.vlen, wr * 64, wc * 64,
+                    lane);
+  if (a.j > 0)
+    wave_gemm<T, T>(acc, ri.panel, ri.ld, ri.nstore, rj.panel, rj.ld, rj.nstore, 0, a.j * TB, wr * 64,
+                    wc * 64, lane);
+
+  const int d = a.d;
+  T* xr = reinterpret_cast<T*>(smem_raw);  // [d][TB] row-side coordinates
+  T* xc = xr + d * TB;                     // [d][TB] column-side coordinates
+  const bool kern = ri.src == SRC_KERNEL;
+  if (kern) {
+    for (int idx = tid; idx < TB * d; idx += NT) {
+      const int r = idx / d, t = idx - r * d;
+      xr[t * TB + r] = r < ri.nvalid ? ri.xs[(int64_t)r * d + t] : T(0);
+      xc[t * TB + r] = r < rj.nvalid ? rj.xs[(int64_t)r * d + t] : T(0);
+    }
+  }
+  __syncthreads();
+  const bool diag = ri.is_j && (it.tile == a.j);
+  const T sf2 = (T)a.sf2, sn2 = (T)a.sn2;
+  T* out = ri.panel + (int64_t)a.j * TB;
+#pragma unroll
+  for (int rs = 0; rs < 4; ++rs) {
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 64 + rs * 16 + Mfma<T>::row(lane, v);
+        const int col = wc * 64 + cs * 16 + (lane & 15);
+        T kv = T(0);
+        if (row < ri.nvalid && col < rj.nvalid) {
+          if (kern) {
+            T s = T(0);
+            for (int t = 0; t < d; ++t) {
+              const T df = xr[t * TB + row] - xc[t * TB + col];
+              s += df * df;
+            }
+            kv = sf2 * k_exp(T(-0.5) * s);
+            if (diag && row == col) kv += sn2;
+          } else if (ri.src == SRC_EXPLICIT) {
+            kv = ri.expl[(int64_t)row * ri.eld + (int64_t)a.j * TB + col];
+          } else {
+            kv = row == 0 ? rj.cv[col] : T(0);
+          }
+        } else if (diag && row == col) {
+          kv = T(1);
+        }
+        if (row < ri.nstore) out[(int64_t)row * ri.ld + col] = kv - acc[rs][cs][v];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// diag: Cholesky of the diagonal tile (j, j) in LDS, its log-diagonal, and the
+// inverse of the factor for the triangular solves of the tiles below.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_diag(StepArgs<T> a, const int32_t* __restrict__ plist) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* A = reinterpret_cast<T*>(smem_raw);  // [TB][DIAG_LD]
+  T* col0 = A + TB * DIAG_LD;             // [TB] double-buffered column copies
+  T* col1 = col0 + TB;
+  T* part = col1 + TB;                    // [2][TB] partial dot products
+  __shared__ int bad;
+  __shared__ double lsum[NT / 64];
+  const int p = plist[blockIdx.x];
+  const ProbDesc pd = a.pd[p];
+  const RowTile<T> rj = a.rt[pd.first + a.j];
+  T* src = rj.panel + (int64_t)a.j * TB;
+  const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
+  for (int idx = tid; idx < TB * TB; idx += NT) {
+    const int r = idx >> 7, c = idx & (TB - 1);
+    A[r * DIAG_LD + c] = c <= r ? src[(int64_t)r * rj.ld + c] : T(0);
+  }
+  __syncthreads();
+  // Right-looking factorisation; the column scaling of step k runs
+  // concurrently with the trailing update of step k+1 (disjoint columns).
+  const int tr = tid >> 4, tc = tid & 15;
+  for (int k = 0; k < TB; ++k) {
+    T dkk = A[k * DIAG_LD + k];
+    const bool ok = dkk > T(0);
+    if (!ok) dkk = T(1);
+    const T rinv = T(1) / dkk;
+    for (int r = k + 1 + tr; r < TB; r += 16) {
+      const T lrk = A[r * DIAG_LD + k] * rinv;
+      for (int c = k + 1 + tc; c <= r; c += 16) A[r * DIAG_LD + c] -= lrk * A[c * DIAG_LD + k];
+    }
+    __syncthreads();
+    const T piv = k_sqrt(dkk), ip = T(1) / piv;
+    for (int r = k + 1 + tid; r < TB; r += NT) A[r * DIAG_LD + k] *= ip;
+    if (tid == 0) {
+      A[k * DIAG_LD + k] = piv;
+      if (!ok) bad = 1;
+    }
+  }
+  __syncthreads();
+  if (bad && tid == 0) a.status[p] = 1;
+  // store L_jj and its log-diagonal
+  for (int idx = tid; idx < TB * TB; idx += NT) {
+    const int r = idx >> 7, c = idx & (TB - 1);
+    src[(int64_t)r * rj.ld + c] = c <= r ? A[r * DIAG_LD + c] : T(0);
+  }
+  {
+    double ls = 0.0;
+    if (tid < TB && tid < rj.nvalid) ls = log((double)A[tid * DIAG_LD + tid]);
+    for (int o = 32; o > 0; o >>= 1) ls += __shfl_xor(ls, o);
+    if ((tid & 63) == 0) lsum[tid >> 6] = ls;
+  }
+  // in-place inverse of the lower-triangular factor, last column first:
+  //   X_jj = 1/L_jj,  X_{r,jj} = -X_jj * sum_{k=jj+1}^{r} X_rk L_{k,jj}
+  for (int r = tid; r < TB; r += NT) col0[r] = A[r * DIAG_LD + (TB - 1)];
+  __syncthreads();
+  if (tid == 0) {
+    const double tot = lsum[0] + lsum[1] + lsum[2] + lsum[3];
+    a.logdiag[(int64_t)p * a.maxT + a.j] = (a.j >= pd.ld_from) ? tot : 0.0;
+  }
+  for (int jj = TB - 1; jj >= 0; --jj) {
+    T* cur = ((TB - 1 - jj) & 1) ? col1 : col0;   // old column jj (rows > jj valid)
+    T* nxt = ((TB - 1 - jj) & 1) ? col0 : col1;
+    const T xjj = T(1) / A[jj * DIAG_LD + jj];      // not written before the next barrier
+    {
+      const int r = jj + 1 + (tid >> 1), h = tid & 1;
+      T s = T(0);
+      if (r < TB) {
+        for (int k = jj + 1 + h; k <= r; k += 2) s += A[r * DIAG_LD + k] * cur[k];
+        part[h * TB + r] = s;
+      }
+    }
+    __syncthreads();
+    for (int r = jj + 1 + tid; r < TB; r += NT) A[r * DIAG_LD + jj] = -xjj * (part[r] + part[TB + r]);
+    if (tid == 0) A[jj * DIAG_LD + jj] = xjj;
+    if (jj > 0)
+      for (int r = tid; r < TB; r += NT) nxt[r] = r >= jj ? A[r * DIAG_LD + (jj - 1)] : T(0);
+    __syncthreads();
+  }
+  __syncthreads();
+  T* inv = a.invdiag + pd.invdiag_off + (int64_t)a.j * TB * TB;
+  for (int idx = tid; idx < TB * TB; idx += NT) {
+    const int r = idx >> 7, c = idx & (TB - 1);
+    inv[idx] = c <= r ? A[r * DIAG_LD + c] : T(0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// trsm: L_ij = C_ij L_jj^-T (in place) for every item (p, i), i != j
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_trsm(StepArgs<T> a) {
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  if (logical >= a.nitems) return;
+  const WorkItem it = a.items[logical];
+  const ProbDesc pd = a.pd[it.p];
+  const RowTile<T> ri = a.rt[pd.first + it.tile];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  T* C = ri.panel + (int64_t)a.j * TB;
+  const T* Li = a.invdiag + pd.invdiag_off + (int64_t)a.j * TB * TB;
+  typename Mfma<T>::acc acc[4][4];
+  zero_acc<T>(acc);
+  wave_gemm<T, T>(acc, C, ri.ld, ri.nstore, Li, TB, TB, 0, TB, wr * 64, wc * 64, lane);
+  __syncthreads();  // every wave has consumed its reads of C before anyone overwrites it
+#pragma unroll
+  for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 64 + rs * 16 + Mfma<T>::row(lane, v);
+        const int col = wc * 64 + cs * 16 + (lane & 15);
+        if (row < ri.nstore) C[(int64_t)row * ri.ld + col] = acc[rs][cs][v];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// batched float64-accumulating tile GEMM
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_tile_gemm(const GemmTerm<T>* __restrict__ terms,
+                                                  const GemmOut* __restrict__ outs, int nout) {
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  if (logical >= nout) return;
+  const GemmOut o = outs[logical];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  typename Mfma<double>::acc acc[4][4];
+  zero_acc<double>(acc);
+  for (int t = o.t0; t < o.t1; ++t) {
+    const GemmTerm<T> tm = terms[t];
+    wave_gemm<T, double>(acc, tm.a, tm.lda, tm.anr, tm.b, tm.ldb, tm.bnr, tm.k0, tm.k1, wr * 64, wc * 64,
+                         lane);
+  }
+#pragma unroll
+  for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 64 + rs * 16 + Mfma<double>::row(lane, v);
+        const int col = wc * 64 + cs * 16 + (lane & 15);
+        if (row < o.rows && col < o.cols) {
+          double* q = o.out + (int64_t)row * o.ld + col;
+          *q = o.accumulate ? *q + acc[rs][cs][v] : acc[rs][cs][v];
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static inline int pad8(int n) { return ((n + 7) / 8) * 8; }
+
+template <typename T>
+size_t diag_lds_bytes() {
+  return sizeof(T) * (size_t)(TB * DIAG_LD + 4 * TB);
+}
+
+template <typename T>
+void launch_update(const StepArgs<T>& a, hipStream_t st) {
+  if (a.nitems <= 0) return;
+  const size_t lds = 2 * (size_t)a.d * TB * sizeof(T);
+  hipLaunchKernelGGL(k_update<T>, dim3(pad8(a.nitems)), dim3(NT), lds, st, a);
+}
+
+template <typename T>
+void launch_diag(const StepArgs<T>& a, const int32_t* plist, int np, hipStream_t st) {
+  if (np <= 0) return;
+  hipLaunchKernelGGL(k_diag<T>, dim3(np), dim3(NT), diag_lds_bytes<T>(), st, a, plist);
+}
+
+template <typename T>
+void launch_trsm(const StepArgs<T>& a, hipStream_t st) {
+  if (a.nitems <= 0) return;
+  hipLaunchKernelGGL(k_trsm<T>, dim3(pad8(a.nitems)), dim3(NT), 0, st, a);
+}
+
+template <typename T>
+void launch_tile_gemm(const GemmTerm<T>* terms, const GemmOut* outs, int nout, hipStream_t st) {
+  if (nout <= 0) return;
+  hipLaunchKernelGGL(k_tile_gemm<T>, dim3(pad8(nout)), dim3(NT), 0, st, terms, outs, nout);
+}
+
+// Raise the dynamic-LDS limit of the kernels that need more than the default.
+hipError_t engine_init() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_diag<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)diag_lds_bytes<double>());
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_diag<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)diag_lds_bytes<float>());
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_update<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(2 * 64 * TB * sizeof(double)));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_update<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(2 * 64 * TB * sizeof(float)));
+}
+
+template void launch_update<double>(const StepArgs<double>&, hipStream_t);
+template void launch_update<float>(const StepArgs<float>&, hipStream_t);
+template void launch_diag<double>(const StepArgs<double>&, const int32_t*, int, hipStream_t);
+template void launch_diag<float>(const StepArgs<float>&, const int32_t*, int, hipStream_t);
+template void launch_trsm<double>(const StepArgs<double>&, hipStream_t);
+template void launch_trsm<float>(const StepArgs<float>&, hipStream_t);
+template void launch_tile_gemm<double>(const GemmTerm<double>*, const GemmOut*, int, hipStream_t);
+template void launch_tile_gemm<float>(const GemmTerm<float>*, const GemmOut*, int, hipStream_t);
+
+}  // namespace lma

@@ -1,0 +1,1353 @@
+// Host runtime and C ABI of the LMA library (see include/lma.h).
+//
+// lma_fit, per problem:
+//   1. scale inputs by the length-scales, centre y;
+//   2. S run (float64): Cholesky of Sigma_SS with the training rows as
+//      right-hand sides -> L_SS and V^T = K_DS L_SS^-T (n x sp);
+//   3. window run (float64 or float32): for every block m the window
+//      J_m = [D^B_m ; D_m] is factored with the support rows K_SJ and the
+//      centred outputs c_J as right-hand sides; the residual R_J = Sigma_JJ -
+//      V_J^T V_J is generated tile by tile inside the update kernel
+//      (Lemma 1 / Definition 1 in whitened form);
+//   4. summary GEMM (float64 accumulation) over the D_m columns of every
+//      window: Sigma_ddot_SS - Sigma_SS, y_ddot_S, sum |z_m|^2 (Definition 2);
+//   5. Sigma_ddot run (float64): Cholesky of Sigma_ddot_SS; one-workgroup
+//      solve for g with iterative refinement (Theorem 2).
+// lma_predict: S run and window runs in solve-only mode on the test rows,
+// per-point sums G_u, l_u, xi_u over the windows q-B..q of the test block,
+// Sigma_ddot solve of k_u - G_u, and the combine of Theorem 2.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+#include "lma.h"
+#include "misc.h"
+
+using namespace lma;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local int64_t g_failed = 0;
+
+struct Err {
+  lma_status st;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                          \
+  do {                                                                                     \
+    hipError_t e_ = (x);                                                                   \
+    if (e_ != hipSuccess)                                                                  \
+      throw Err{LMA_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)};                \
+  } while (0)
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t align_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+// One device allocation per state, carved into 256-byte aligned pieces.
+struct Arena {
+  char* base = nullptr;
+  int64_t cap = 0, used = 0;
+  int64_t reserve(int64_t bytes) {
+    const int64_t off = used;
+    used += align_up(bytes, 256);
+    return off;
+  }
+};
+
+template <typename T>
+T* at(const Arena& ar, int64_t off) {
+  return reinterpret_cast<T*>(ar.base + off);
+}
+
+bool g_inited = false;
+void ensure_init() {
+  if (g_inited) return;
+  HIPCHK(engine_init());
+  HIPCHK(misc_init());
+  g_inited = true;
+}
+
+// ---------------------------------------------------------------------------
+// live timing: HIP events around launches (enabled by lma_profile_enable)
+// ---------------------------------------------------------------------------
+namespace prof {
+enum Kind { UPDATE = 0, DIAG = 1, TRSM = 2, OTHER = 3 };
+bool on = false;
+struct Rec {
+  int kind;
+  hipEvent_t a, b;
+  double flops;
+};
+std::vector<Rec> pending;
+std::vector<hipEvent_t> pool;
+lma_profile acc = {};
+hipEvent_t get() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+template <class F>
+void timed(int kind, double flops, hipStream_t st, F&& launch) {
+  if (!on) {
+    launch();
+    return;
+  }
+  Rec r{kind, get(), get(), flops};
+  HIPCHK(hipEventRecord(r.a, st));
+  launch();
+  HIPCHK(hipEventRecord(r.b, st));
+  pending.push_back(r);
+}
+// call after the stream has been synchronised
+void flush() {
+  for (const Rec& r : pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
+    switch (r.kind) {
+      case UPDATE:
+        acc.update_ms += ms;
+        acc.update_alg_flops += r.flops;
+        acc.update_launches += 1;
+        break;
+      case DIAG: acc.diag_ms += ms; break;
+      case TRSM: acc.trsm_ms += ms; break;
+      default:
+        acc.other_ms += ms;
+        acc.other_launches += 1;
+    }
+    pool.push_back(r.a);
+    pool.push_back(r.b);
+  }
+  pending.clear();
+}
+}  // namespace prof
+
+// Lock-step column schedule of one engine run, uploaded once.
+template <typename T>
+struct Run {
+  std::vector<ProbDesc> pd;
+  std::vector<RowTile<T>> rt;
+  std::vector<uint8_t> solve_only;
+  std::vector<int32_t> status_block;  // block index reported for each problem
+  int maxT = 0;
+  // schedule
+  std::vector<WorkItem> items;
+  std::vector<int32_t> plist;
+  std::vector<int64_t> upd_off, upd_n, trs_off, trs_n, pl_off, pl_n;
+  // device copies
+  RowTile<T>* d_rt = nullptr;
+  ProbDesc* d_pd = nullptr;
+  WorkItem* d_items = nullptr;
+  int32_t* d_plist = nullptr;
+  int64_t invdiag_elems = 0;
+
+  int add_problem(int T_, int R, int ld_from, bool so, int block) {
+    ProbDesc p;
+    p.T = T_;
+    p.R = R;
+    p.first = (int32_t)rt.size();
+    p.ld_from = ld_from;
+    p.invdiag_off = invdiag_elems;
+    invdiag_elems += (int64_t)T_ * TB * TB;
+    pd.push_back(p);
+    solve_only.push_back(so ? 1 : 0);
+    status_block.push_back(block);
+    maxT = std::max(maxT, T_);
+    return (int)pd.size() - 1;
+  }
+
+  void schedule() {
+    const int np = (int)pd.size();
+    upd_off.assign(maxT, 0);
+    upd_n.assign(maxT, 0);
+    trs_off.assign(maxT, 0);
+    trs_n.assign(maxT, 0);
+    pl_off.assign(maxT, 0);
+    pl_n.assign(maxT, 0);
+    for (int j = 0; j < maxT; ++j) {
+      upd_off[j] = (int64_t)items.size();
+      for (int p = 0; p < np; ++p) {
+        if (pd[p].T <= j) continue;
+        if (!solve_only[p])
+          for (int i = j; i < pd[p].T; ++i) items.push_back({p, i});
+        for (int r = 0; r < pd[p].R; ++r) items.push_back({p, pd[p].T + r});
+      }
+      upd_n[j] = (int64_t)items.size() - upd_off[j];
+      trs_off[j] = (int64_t)items.size();
+      for (int p = 0; p < np; ++p) {
+        if (pd[p].T <= j) continue;
+        if (!solve_only[p])
+          for (int i = j + 1; i < pd[p].T; ++i) items.push_back({p, i});
+        for (int r = 0; r < pd[p].R; ++r) items.push_back({p, pd[p].T + r});
+      }
+      trs_n[j] = (int64_t)items.size() - trs_off[j];
+      pl_off[j] = (int64_t)plist.size();
+      for (int p = 0; p < np; ++p)
+        if (pd[p].T > j && !solve_only[p]) plist.push_back(p);
+      pl_n[j] = (int64_t)plist.size() - pl_off[j];
+    }
+  }
+
+  // multiply-adds (x2) of the update launch of step j on real entries only
+  double update_flops(int j, int64_t s_valid) const {
+    double f = 0.0;
+    for (int64_t t = upd_off[j]; t < upd_off[j] + upd_n[j]; ++t) {
+      const WorkItem it = items[t];
+      const ProbDesc& p = pd[it.p];
+      const RowTile<T>& ri = rt[p.first + it.tile];
+      const RowTile<T>& rj = rt[p.first + j];
+      double K = (ri.vt && rj.vt) ? (double)s_valid : 0.0;
+      for (int k = 0; k < j; ++k) K += rt[p.first + k].nvalid;
+      const double rows = ri.nvalid, cols = rj.nvalid;
+      const double pairs = (ri.is_j && it.tile == j) ? rows * (rows + 1) / 2 : rows * cols;
+      f += 2.0 * pairs * K;
+    }
+    return f;
+  }
+
+  int64_t meta_bytes() const {
+    return align_up(sizeof(RowTile<T>) * rt.size(), 256) + align_up(sizeof(ProbDesc) * pd.size(), 256) +
+           align_up(sizeof(WorkItem) * std::max<size_t>(items.size(), 1), 256) +
+           align_up(sizeof(int32_t) * std::max<size_t>(plist.size(), 1), 256);
+  }
+
+  void upload(char* dst, hipStream_t st) {
+    char* p = dst;
+    d_rt = reinterpret_cast<RowTile<T>*>(p);
+    if (!rt.empty())
+      HIPCHK(hipMemcpyAsync(p, rt.data(), sizeof(RowTile<T>) * rt.size(), hipMemcpyHostToDevice, st));
+    p += align_up(sizeof(RowTile<T>) * rt.size(), 256);
+    d_pd = reinterpret_cast<ProbDesc*>(p);
+    if (!pd.empty())
+      HIPCHK(hipMemcpyAsync(p, pd.data(), sizeof(ProbDesc) * pd.size(), hipMemcpyHostToDevice, st));
+    p += align_up(sizeof(ProbDesc) * pd.size(), 256);
+    d_items = reinterpret_cast<WorkItem*>(p);
+    if (!items.empty())
+      HIPCHK(hipMemcpyAsync(p, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice, st));
+    p += align_up(sizeof(WorkItem) * std::max<size_t>(items.size(), 1), 256);
+    d_plist = reinterpret_cast<int32_t*>(p);
+    if (!plist.empty())
+      HIPCHK(hipMemcpyAsync(p, plist.data(), sizeof(int32_t) * plist.size(), hipMemcpyHostToDevice, st));
+  }
+
+  void execute(T* invdiag, double* logdiag, int32_t* status, int vlen, int64_t vld, int d, double sf2,
+               double sn2, hipStream_t st) {
+    StepArgs<T> a;
+    a.rt = d_rt;
+    a.pd = d_pd;
+    a.vlen = vlen;
+    a.vld = vld;
+    a.d = d;
+    a.sf2 = sf2;
+    a.sn2 = sn2;
+    a.invdiag = invdiag;
+    a.logdiag = logdiag;
+    a.status = status;
+    a.maxT = maxT;
+    for (int j = 0; j < maxT; ++j) {
+      a.j = j;
+      a.items = d_items + upd_off[j];
+      a.nitems = (int32_t)upd_n[j];
+      launch_update<T>(a, st);
+      HIPCHK(hipGetLastError());
+      launch_diag<T>(a, d_plist + pl_off[j], (int)pl_n[j], st);
+      HIPCHK(hipGetLastError());
+      a.items = d_items + trs_off[j];
+      a.nitems = (int32_t)trs_n[j];
+      launch_trsm<T>(a, st);
+      HIPCHK(hipGetLastError());
+    }
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// state
+// ---------------------------------------------------------------------------
+struct lma_state {
+  int precision = 0;
+  int64_t n = 0, d = 0, s = 0, M = 0, B = 0, sp = 0, Ts = 0;
+  double mu = 0, sf2 = 0, sn2 = 0;
+  std::vector<double> log_hyp;
+  InvEll ie;
+  std::vector<int64_t> bp;
+  Arena ar;
+  // offsets in the arena
+  int64_t o_Xs64 = -1, o_Xs32 = -1, o_Ss64 = -1, o_Ss32 = -1, o_c64 = -1, o_c32 = -1;
+  int64_t o_Vt64 = -1, o_Vt32 = -1, o_Lss = -1, o_Lss_inv = -1;
+  int64_t o_win = -1, o_win_inv = -1, o_partial = -1, o_Sdd = -1, o_ydd = -1, o_q = -1;
+  int64_t o_Ldd = -1, o_Ldd_inv = -1, o_g = -1, o_logdiag = -1, o_status = -1, o_meta = -1;
+  int64_t n_logdiag = 0, n_status = 0;
+  // mean path: window table, beta vectors and their V-projections
+  int64_t o_wt = -1, o_xJ = -1, o_xW = -1, o_tJ = -1, o_tW = -1, o_rJ = -1, o_rW = -1, o_hJ = -1, o_hW = -1,
+          o_cg = -1, vec_elems = 0;
+  WinTab wt;
+  // window geometry
+  std::vector<int32_t> Tm, twm;
+  std::vector<int64_t> win_off;     // element offset of window m's panels
+  std::vector<int64_t> rhs_off;     // element offset of window m's RHS panel (support rows then c row)
+  int groups = 1, ntile = 1;
+  // runs
+  Run<double> runS;
+  Run<float> runW32;
+  Run<double> runW64;
+  Run<double> runD;
+  std::vector<GemmTerm<double>> sum64;
+  std::vector<GemmTerm<float>> sum32;
+  std::vector<GemmOut> sumout;
+  std::vector<int64_t> wt_host;
+  int64_t o_sumterms = -1, o_sumout = -1;
+  // results
+  std::vector<double> g, ydd;
+  double qsum = 0, ld_R = 0, ld_ss = 0, ld_dd = 0, ydg = 0, lml = 0;
+
+  ~lma_state() {
+    if (ar.base) (void)hipFree(ar.base);
+  }
+  bool mixed() const { return precision == LMA_MIXED; }
+  template <typename T>
+  T* ptr(int64_t off) const {
+    return off < 0 ? nullptr : at<T>(ar, off);
+  }
+};
+
+namespace {
+
+void check_problem(const lma_problem* p) {
+  if (!p) throw Err{LMA_E_ARG, "problem is NULL"};
+  if (p->n < 1 || p->d < 1 || p->d > MAX_D || p->s < 1 || p->M < 1 || p->B < 0)
+    throw Err{LMA_E_ARG, "need n >= 1, 1 <= d <= 64, s >= 1, M >= 1, B >= 0"};
+  if (p->M > p->n) throw Err{LMA_E_ARG, "more blocks than training inputs"};
+  if (align_up(p->s, TB) > MAX_SP) throw Err{LMA_E_ARG, "support set larger than 8192"};
+  if (!p->X || !p->y || !p->S || !p->block_ptr || !p->log_hyp) throw Err{LMA_E_ARG, "NULL array"};
+  if (p->precision != LMA_FP64 && p->precision != LMA_MIXED) throw Err{LMA_E_ARG, "unknown precision"};
+  if (p->reserved != 0) throw Err{LMA_E_ARG, "reserved field must be 0"};
+  if (p->block_ptr[0] != 0 || p->block_ptr[p->M] != p->n)
+    throw Err{LMA_E_ARG, "block_ptr must start at 0 and end at n"};
+  for (int64_t m = 0; m < p->M; ++m)
+    if (p->block_ptr[m + 1] <= p->block_ptr[m]) throw Err{LMA_E_ARG, "blocks must be non-empty and increasing"};
+  for (int64_t t = 0; t < p->d + 2; ++t)
+    if (!std::isfinite(p->log_hyp[t])) throw Err{LMA_E_ARG, "non-finite hyperparameter"};
+  if (!std::isfinite(p->prior_mean)) throw Err{LMA_E_ARG, "non-finite prior mean"};
+}
+
+// Row-tile panel layout of a problem with T column tiles and R RHS tiles:
+// J row tile i holds tiles (i, 0..i) with ld (i+1)*TB; RHS row tile r holds
+// tiles (T+r, 0..T-1) with ld T*TB.
+inline int64_t jpanel_off(int i) { return (int64_t)TB * TB * i * (i + 1) / 2; }
+inline int64_t panel_elems(int T_, int R) { return jpanel_off(T_) + (int64_t)R * TB * T_ * TB; }
+
+template <typename T>
+RowTile<T> make_tile(T* panel, int64_t ld, const T* vt, const T* xs, const T* cv, int nvalid, int nstore, int src,
+                     int is_j) {
+  RowTile<T> r;
+  r.panel = panel;
+  r.ld = ld;
+  r.vt = vt;
+  r.xs = xs;
+  r.cv = cv;
+  r.expl = nullptr;
+  r.eld = 0;
+  r.nvalid = nvalid;
+  r.nstore = nstore;
+  r.src = src;
+  r.is_j = is_j;
+  return r;
+}
+
+// Window m: W_m = blocks m+1 .. min(m+B, M-1), then D_m.
+struct WinGeom {
+  int64_t wstart, w, dstart, b;
+  int tw, tb, T;
+};
+WinGeom win_geom(const std::vector<int64_t>& bp, int64_t M, int64_t B, int64_t m) {
+  WinGeom g;
+  const int64_t hi = std::min(m + B, M - 1);
+  g.wstart = bp[m + 1 <= M ? m + 1 : M];
+  g.w = hi > m ? bp[hi + 1] - bp[m + 1] : 0;
+  g.dstart = bp[m];
+  g.b = bp[m + 1] - bp[m];
+  g.tw = (int)cdiv(g.w, TB);
+  g.tb = (int)cdiv(g.b, TB);
+  g.T = g.tw + g.tb;
+  return g;
+}
+
+// J row tiles of window m (descriptors shared by fit and predict runs).
+template <typename T>
+void add_window_jtiles(std::vector<RowTile<T>>& rt, const WinGeom& g, T* base, const T* Xs, const T* Vt,
+                       const T* c, int64_t d, int64_t sp) {
+  for (int i = 0; i < g.T; ++i) {
+    int64_t pt;
+    int nv;
+    if (i < g.tw) {
+      pt = g.wstart + (int64_t)i * TB;
+      nv = (int)std::min<int64_t>(TB, g.w - (int64_t)i * TB);
+    } else {
+      pt = g.dstart + (int64_t)(i - g.tw) * TB;
+      nv = (int)std::min<int64_t>(TB, g.b - (int64_t)(i - g.tw) * TB);
+    }
+    rt.push_back(make_tile<T>(base + jpanel_off(i), (int64_t)(i + 1) * TB, Vt + pt * sp, Xs + pt * d, c + pt, nv,
+                              TB, SRC_KERNEL, 1));
+  }
+}
+
+template <typename T>
+void add_s_jtiles(std::vector<RowTile<T>>& rt, T* base, const T* Ss, int64_t s, int64_t d, int Ts) {
+  for (int i = 0; i < Ts; ++i) {
+    const int nv = (int)std::min<int64_t>(TB, s - (int64_t)i * TB);
+    rt.push_back(make_tile<T>(base + jpanel_off(i), (int64_t)(i + 1) * TB, nullptr, Ss + (int64_t)i * TB * d,
+                              nullptr, nv, TB, SRC_KERNEL, 1));
+  }
+}
+
+void set_err(const Err& e) {
+  g_err = e.msg;
+}
+
+// ---------------------------------------------------------------------------
+// fit
+// ---------------------------------------------------------------------------
+template <typename TW>
+void build_window_run(lma_state& f, Run<TW>& run, TW* winbase, const TW* Xs, const TW* Vt, const TW* c,
+                      const TW* Ss) {
+  const int Ts = (int)f.Ts;
+  for (int64_t m = 0; m < f.M; ++m) {
+    const WinGeom g = win_geom(f.bp, f.M, f.B, m);
+    TW* base = winbase + f.win_off[m];
+    run.add_problem(g.T, Ts + 1, g.tw, false, (int)m);
+    add_window_jtiles<TW>(run.rt, g, base, Xs, Vt, c, f.d, f.sp);
+    TW* rhs = base + jpanel_off(g.T);
+    const int64_t ld = (int64_t)g.T * TB;
+    for (int r = 0; r < Ts; ++r) {
+      const int nv = (int)std::min<int64_t>(TB, f.s - (int64_t)r * TB);
+      run.rt.push_back(make_tile<TW>(rhs + (int64_t)r * TB * ld, ld, nullptr, Ss + (int64_t)r * TB * f.d, nullptr,
+                                     nv, TB, SRC_KERNEL, 0));
+    }
+    run.rt.push_back(make_tile<TW>(rhs + (int64_t)Ts * TB * ld, ld, nullptr, nullptr, nullptr, 1, TB, SRC_CVEC, 0));
+  }
+}
+
+template <typename TW>
+void build_summary(lma_state& f, std::vector<GemmTerm<TW>>& terms, TW* winbase) {
+  const int Ts = (int)f.Ts;
+  const int nt = Ts + 1;
+  f.ntile = nt * (nt + 1) / 2;
+  f.groups = (int)std::max<int64_t>(1, std::min<int64_t>(f.M, cdiv(1024, f.ntile)));
+  const int64_t per = cdiv(f.M, f.groups);
+  f.groups = (int)cdiv(f.M, per);
+  double* partial = f.ptr<double>(f.o_partial);
+  f.sumout.clear();
+  terms.clear();
+  for (int gi = 0; gi < f.groups; ++gi) {
+    const int64_t m0 = gi * per, m1 = std::min<int64_t>(f.M, m0 + per);
+    for (int ta = 0; ta < nt; ++ta)
+      for (int tb = 0; tb <= ta; ++tb) {
+        const int t = ta * (ta + 1) / 2 + tb;
+        GemmOut o;
+        o.out = partial + ((int64_t)gi * f.ntile + t) * TB * TB;
+        o.ld = TB;
+        o.rows = TB;
+        o.cols = TB;
+        o.accumulate = 0;
+        o.t0 = (int32_t)terms.size();
+        for (int64_t m = m0; m < m1; ++m) {
+          const WinGeom g = win_geom(f.bp, f.M, f.B, m);
+          TW* rhs = winbase + f.win_off[m] + jpanel_off(g.T);
+          const int64_t ld = (int64_t)g.T * TB;
+          GemmTerm<TW> tm;
+          tm.a = rhs + (int64_t)ta * TB * ld;
+          tm.lda = ld;
+          tm.anr = TB;
+          tm.b = rhs + (int64_t)tb * TB * ld;
+          tm.ldb = ld;
+          tm.bnr = TB;
+          tm.k0 = g.tw * TB;
+          tm.k1 = g.T * TB;
+          terms.push_back(tm);
+        }
+        o.t1 = (int32_t)terms.size();
+        f.sumout.push_back(o);
+      }
+  }
+}
+
+lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool keep) {
+  check_problem(p);
+  ensure_init();
+  std::unique_ptr<lma_state> F(new lma_state());
+  lma_state& f = *F;
+  f.precision = p->precision;
+  f.n = p->n;
+  f.d = p->d;
+  f.s = p->s;
+  f.M = p->M;
+  f.B = std::min<int64_t>(p->B, p->M - 1);
+  f.sp = align_up(p->s, TB);
+  f.Ts = f.sp / TB;
+  f.mu = p->prior_mean;
+  f.log_hyp.assign(p->log_hyp, p->log_hyp + p->d + 2);
+  for (int t = 0; t < MAX_D; ++t) f.ie.v[t] = t < p->d ? std::exp(-p->log_hyp[t]) : 0.0;
+  f.sf2 = std::exp(p->log_hyp[p->d]);
+  f.sn2 = std::exp(p->log_hyp[p->d + 1]);
+  f.bp.assign(p->block_ptr, p->block_ptr + p->M + 1);
+  const bool mixed = f.mixed();
+  const int64_t n = f.n, d = f.d, s = f.s, sp = f.sp, M = f.M;
+  const int Ts = (int)f.Ts;
+  const int64_t wsz = mixed ? 4 : 8;
+
+  // ---- geometry and memory plan
+  Arena& ar = f.ar;
+  f.o_Xs64 = ar.reserve(8 * n * d);
+  f.o_Ss64 = ar.reserve(8 * s * d);
+  f.o_c64 = ar.reserve(8 * n);
+  if (mixed) {
+    f.o_Xs32 = ar.reserve(4 * n * d);
+    f.o_Ss32 = ar.reserve(4 * s * d);
+    f.o_c32 = ar.reserve(4 * n);
+    f.o_Vt32 = ar.reserve(4 * n * sp);
+  }
+  f.o_Vt64 = ar.reserve(8 * n * sp);
+  f.o_Lss = ar.reserve(8 * panel_elems(Ts, 0));
+  f.o_Lss_inv = ar.reserve(8 * (int64_t)Ts * TB * TB);
+  f.Tm.resize(M);
+  f.twm.resize(M);
+  f.win_off.resize(M);
+  int64_t win_elems = 0, inv_elems = 0;
+  int maxT = 0;
+  for (int64_t m = 0; m < M; ++m) {
+    const WinGeom g = win_geom(f.bp, M, f.B, m);
+    f.Tm[m] = g.T;
+    f.twm[m] = g.tw;
+    f.win_off[m] = win_elems;
+    win_elems += panel_elems(g.T, Ts + 1);
+    inv_elems += (int64_t)g.T * TB * TB;
+    maxT = std::max(maxT, g.T);
+  }
+  f.o_win = ar.reserve(wsz * win_elems);
+  f.o_win_inv = ar.reserve(wsz * inv_elems);
+  {
+    const int nt = Ts + 1, ntile = nt * (nt + 1) / 2;
+    int groups = (int)std::max<int64_t>(1, std::min<int64_t>(M, cdiv(1024, ntile)));
+    groups = (int)cdiv(M, cdiv(M, groups));
+    f.o_partial = ar.reserve(8 * (int64_t)groups * ntile * TB * TB);
+  }
+  f.o_Sdd = ar.reserve(8 * sp * sp);
+  f.o_ydd = ar.reserve(8 * sp);
+  f.o_q = ar.reserve(8);
+  f.o_Ldd = ar.reserve(8 * panel_elems(Ts, 0));
+  f.o_Ldd_inv = ar.reserve(8 * (int64_t)Ts * TB * TB);
+  f.o_g = ar.reserve(8 * sp);
+  f.n_logdiag = (int64_t)(M + 2) * std::max(maxT, Ts);
+  f.o_logdiag = ar.reserve(8 * f.n_logdiag);
+  f.n_status = M + 2;
+  f.o_status = ar.reserve(4 * f.n_status);
+  f.vec_elems = 0;
+  for (int64_t m = 0; m < M; ++m) f.vec_elems += (int64_t)f.Tm[m] * TB;
+  f.o_wt = ar.reserve(8 * 9 * M);
+  f.o_xJ = ar.reserve(8 * f.vec_elems);
+  f.o_xW = ar.reserve(8 * f.vec_elems);
+  f.o_tJ = ar.reserve(8 * f.vec_elems);
+  f.o_tW = ar.reserve(8 * f.vec_elems);
+  if (mixed) {
+    f.o_rJ = ar.reserve(8 * f.vec_elems);
+    f.o_rW = ar.reserve(8 * f.vec_elems);
+  }
+  f.o_hJ = ar.reserve(8 * M * sp);
+  f.o_hW = ar.reserve(8 * M * sp);
+  f.o_cg = ar.reserve(8 * n);
+
+  // engine runs (built with arena offsets; pointers fixed after allocation)
+  // Reserve space for run metadata: build runs against a null base first to size them.
+  auto build_runs = [&](char* base) {
+    f.ar.base = base;
+    f.runS = Run<double>();
+    f.runW32 = Run<float>();
+    f.runW64 = Run<double>();
+    f.runD = Run<double>();
+    // S run: Sigma_SS with the training rows as right-hand sides
+    const int Rn = (int)cdiv(n, TB);
+    f.runS.add_problem(Ts, Rn, 0, false, -1);
+    add_s_jtiles<double>(f.runS.rt, f.ptr<double>(f.o_Lss), f.ptr<double>(f.o_Ss64), s, d, Ts);
+    for (int r = 0; r < Rn; ++r) {
+      const int nv = (int)std::min<int64_t>(TB, n - (int64_t)r * TB);
+      f.runS.rt.push_back(make_tile<double>(f.ptr<double>(f.o_Vt64) + (int64_t)r * TB * sp, sp, nullptr,
+                                            f.ptr<double>(f.o_Xs64) + (int64_t)r * TB * d, nullptr, nv, nv,
+                                            SRC_KERNEL, 0));
+    }
+    f.runS.schedule();
+    // window run
+    if (mixed) {
+      build_window_run<float>(f, f.runW32, f.ptr<float>(f.o_win), f.ptr<float>(f.o_Xs32), f.ptr<float>(f.o_Vt32),
+                              f.ptr<float>(f.o_c32), f.ptr<float>(f.o_Ss32));
+      f.runW32.schedule();
+      build_summary<float>(f, f.sum32, f.ptr<float>(f.o_win));
+    } else {
+      build_window_run<double>(f, f.runW64, f.ptr<double>(f.o_win), f.ptr<double>(f.o_Xs64),
+                               f.ptr<double>(f.o_Vt64), f.ptr<double>(f.o_c64), f.ptr<double>(f.o_Ss64));
+      f.runW64.schedule();
+      build_summary<double>(f, f.sum64, f.ptr<double>(f.o_win));
+    }
+    // Sigma_ddot run (explicit matrix, no right-hand sides)
+    f.runD.add_problem(Ts, 0, 0, false, -2);
+    for (int i = 0; i < Ts; ++i) {
+      const int nv = (int)std::min<int64_t>(TB, s - (int64_t)i * TB);
+      RowTile<double> r = make_tile<double>(f.ptr<double>(f.o_Ldd) + jpanel_off(i), (int64_t)(i + 1) * TB, nullptr,
+                                            nullptr, nullptr, nv, TB, SRC_EXPLICIT, 1);
+      r.expl = f.ptr<double>(f.o_Sdd) + (int64_t)i * TB * sp;
+      r.eld = sp;
+      f.runD.rt.push_back(r);
+    }
+    f.runD.schedule();
+  };
+  build_runs(nullptr);
+  const int64_t meta = f.runS.meta_bytes() + (mixed ? f.runW32.meta_bytes() : f.runW64.meta_bytes()) +
+                       f.runD.meta_bytes();
+  const int64_t sterm_bytes = mixed ? sizeof(GemmTerm<float>) * f.sum32.size() : sizeof(GemmTerm<double>) * f.sum64.size();
+  f.o_meta = ar.reserve(meta);
+  f.o_sumterms = ar.reserve(sterm_bytes);
+  f.o_sumout = ar.reserve(sizeof(GemmOut) * f.sumout.size());
+  f.ar.cap = f.ar.used;
+  if (p->mem_budget_bytes > 0 && f.ar.cap > p->mem_budget_bytes) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "state needs %lld bytes, over the budget of %lld", (long long)f.ar.cap,
+             (long long)p->mem_budget_bytes);
+    throw Err{LMA_E_NOMEM, buf};
+  }
+  {
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, (size_t)f.ar.cap);
+    if (e != hipSuccess || !mem) {
+      (void)hipGetLastError();
+      char buf[160];
+      snprintf(buf, sizeof buf, "hipMalloc of %lld bytes failed", (long long)f.ar.cap);
+      throw Err{LMA_E_NOMEM, buf};
+    }
+    f.ar.used = f.ar.cap;
+    build_runs(reinterpret_cast<char*>(mem));
+  }
+  // ---- upload schedules
+  {
+    char* mp = f.ptr<char>(f.o_meta);
+    f.runS.upload(mp, st);
+    mp += f.runS.meta_bytes();
+    if (mixed) {
+      f.runW32.upload(mp, st);
+      mp += f.runW32.meta_bytes();
+    } else {
+      f.runW64.upload(mp, st);
+      mp += f.runW64.meta_bytes();
+    }
+    f.runD.upload(mp, st);
+    if (mixed)
+      HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_sumterms), f.sum32.data(), sterm_bytes, hipMemcpyHostToDevice, st));
+    else
+      HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_sumterms), f.sum64.data(), sterm_bytes, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_sumout), f.sumout.data(), sizeof(GemmOut) * f.sumout.size(),
+                          hipMemcpyHostToDevice, st));
+  }
+  // ---- compute
+  int32_t* status = f.ptr<int32_t>(f.o_status);
+  double* logdiag = f.ptr<double>(f.o_logdiag);
+  HIPCHK(hipMemsetAsync(status, 0, 4 * f.n_status, st));
+  HIPCHK(hipMemsetAsync(logdiag, 0, 8 * f.n_logdiag, st));
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(p->X, n, (int)d, f.ie, f.ptr<double>(f.o_Xs64), f.ptr<float>(f.o_Xs32), st); });
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(p->S, s, (int)d, f.ie, f.ptr<double>(f.o_Ss64), f.ptr<float>(f.o_Ss32), st); });
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_center(p->y, n, f.mu, f.ptr<double>(f.o_c64), f.ptr<float>(f.o_c32), st); });
+  HIPCHK(hipGetLastError());
+  const int maxTld = (int)(f.n_logdiag / (M + 2));
+  // Runs share one logdiag stride (maxTld); set it before executing.
+  auto run_with_stride = [&](auto& run, auto* invdiag, int slot, int vlen) {
+    const int realT = run.maxT;
+    using TT = typename std::remove_pointer<decltype(invdiag)>::type;
+    StepArgs<TT> a;
+    a.rt = run.d_rt;
+    a.pd = run.d_pd;
+    a.vlen = vlen;
+    a.vld = sp;
+    a.d = (int)d;
+    a.sf2 = f.sf2;
+    a.sn2 = f.sn2;
+    a.invdiag = invdiag;
+    a.logdiag = logdiag + (int64_t)slot * maxTld;
+    a.status = status + slot;
+    a.maxT = maxTld;
+    for (int j = 0; j < realT; ++j) {
+      a.j = j;
+      a.items = run.d_items + run.upd_off[j];
+      a.nitems = (int32_t)run.upd_n[j];
+      prof::timed(prof::UPDATE, prof::on ? run.update_flops(j, vlen > 0 ? s : 0) : 0.0, st,
+                  [&] { launch_update<TT>(a, st); });
+      HIPCHK(hipGetLastError());
+      prof::timed(prof::DIAG, 0.0, st, [&] { launch_diag<TT>(a, run.d_plist + run.pl_off[j], (int)run.pl_n[j], st); });
+      HIPCHK(hipGetLastError());
+      a.items = run.d_items + run.trs_off[j];
+      a.nitems = (int32_t)run.trs_n[j];
+      prof::timed(prof::TRSM, 0.0, st, [&] { launch_trsm<TT>(a, st); });
+      HIPCHK(hipGetLastError());
+    }
+  };
+  run_with_stride(f.runS, f.ptr<double>(f.o_Lss_inv), (int)M, 0);
+  if (mixed) {
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_cast(f.ptr<double>(f.o_Vt64), f.ptr<float>(f.o_Vt32), n * sp, st); });
+    run_with_stride(f.runW32, f.ptr<float>(f.o_win_inv), 0, (int)sp);
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_tile_gemm<float>(reinterpret_cast<const GemmTerm<float>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
+  } else {
+    run_with_stride(f.runW64, f.ptr<double>(f.o_win_inv), 0, (int)sp);
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_tile_gemm<double>(reinterpret_cast<const GemmTerm<double>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
+  }
+  HIPCHK(hipGetLastError());
+  {
+    SummaryArgs sa;
+    sa.partial = f.ptr<double>(f.o_partial);
+    sa.groups = f.groups;
+    sa.ntile = f.ntile;
+    sa.Ts = Ts;
+    sa.sp = (int)sp;
+    sa.s = (int)s;
+    sa.d = (int)d;
+    sa.Ss = f.ptr<double>(f.o_Ss64);
+    sa.sf2 = f.sf2;
+    sa.sn2 = f.sn2;
+    sa.Sdd = f.ptr<double>(f.o_Sdd);
+    sa.ydd = f.ptr<double>(f.o_ydd);
+    sa.qsum = f.ptr<double>(f.o_q);
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_finalize_summary(sa, st); });
+    HIPCHK(hipGetLastError());
+  }
+  run_with_stride(f.runD, f.ptr<double>(f.o_Ldd_inv), (int)M + 1, 0);
+  {
+    SolveArgs so;
+    so.L = f.ptr<double>(f.o_Ldd);
+    so.inv = f.ptr<double>(f.o_Ldd_inv);
+    so.A = f.ptr<double>(f.o_Sdd);
+    so.b = f.ptr<double>(f.o_ydd);
+    so.g = f.ptr<double>(f.o_g);
+    so.sp = (int)sp;
+    so.iters = 2;
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_global_solve(so, st); });
+    HIPCHK(hipGetLastError());
+  }
+  // ---- beta_X = R_X^-1 (c_X - K_XS g) for every window and separator
+  {
+    std::vector<int64_t> tab(9 * M);
+    int64_t* t_wstart = tab.data();
+    int64_t* t_wlen = t_wstart + M;
+    int64_t* t_dstart = t_wlen + M;
+    int64_t* t_dlen = t_dstart + M;
+    int64_t* t_panel = t_dlen + M;
+    int64_t* t_inv = t_panel + M;
+    int64_t* t_vec = t_inv + M;
+    int32_t* t_T = reinterpret_cast<int32_t*>(t_vec + M);
+    int32_t* t_tw = t_T + M;
+    int64_t inv_acc = 0, vec_acc = 0;
+    for (int64_t m = 0; m < M; ++m) {
+      const WinGeom g = win_geom(f.bp, M, f.B, m);
+      t_wstart[m] = g.wstart;
+      t_wlen[m] = g.w;
+      t_dstart[m] = g.dstart;
+      t_dlen[m] = g.b;
+      t_panel[m] = f.win_off[m];
+      t_inv[m] = inv_acc;
+      t_vec[m] = vec_acc;
+      t_T[m] = g.T;
+      t_tw[m] = g.tw;
+      inv_acc += (int64_t)g.T * TB * TB;
+      vec_acc += (int64_t)g.T * TB;
+    }
+    f.wt_host = tab;
+    char* dt = f.ptr<char>(f.o_wt);
+    HIPCHK(hipMemcpyAsync(dt, f.wt_host.data(), 8 * 9 * M, hipMemcpyHostToDevice, st));
+    const int64_t* dtab = reinterpret_cast<const int64_t*>(dt);
+    f.wt.wstart = dtab;
+    f.wt.wlen = dtab + M;
+    f.wt.dstart = dtab + 2 * M;
+    f.wt.dlen = dtab + 3 * M;
+    f.wt.panel = dtab + 4 * M;
+    f.wt.inv = dtab + 5 * M;
+    f.wt.vec = dtab + 6 * M;
+    f.wt.T = reinterpret_cast<const int32_t*>(dtab + 7 * M);
+    f.wt.tw = f.wt.T + M;
+    CgArgs ca;
+    ca.n = n;
+    ca.d = (int)d;
+    ca.s = (int)s;
+    ca.Xs = f.ptr<double>(f.o_Xs64);
+    ca.Ss = f.ptr<double>(f.o_Ss64);
+    ca.c = f.ptr<double>(f.o_c64);
+    ca.g = f.ptr<double>(f.o_g);
+    ca.sf2 = f.sf2;
+    ca.out = f.ptr<double>(f.o_cg);
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_cg(ca, st); });
+    HIPCHK(hipGetLastError());
+    HArgs ha;
+    ha.w = f.wt;
+    ha.Vt = f.ptr<double>(f.o_Vt64);
+    ha.xJ = f.ptr<double>(f.o_xJ);
+    ha.xW = f.ptr<double>(f.o_xW);
+    ha.hJ = f.ptr<double>(f.o_hJ);
+    ha.hW = f.ptr<double>(f.o_hW);
+    ha.sp = (int)sp;
+    ha.M = (int)M;
+    auto solve = [&](const double* rhs_pt, const double* rJ, const double* rW, int accumulate) {
+      if (mixed) {
+        VecSolveArgs<float> va;
+        va.w = f.wt;
+        va.panels = f.ptr<float>(f.o_win);
+        va.invs = f.ptr<float>(f.o_win_inv);
+        va.rhs_pt = rhs_pt;
+        va.rhsJ = rJ;
+        va.rhsW = rW;
+        va.tJ = f.ptr<double>(f.o_tJ);
+        va.tW = f.ptr<double>(f.o_tW);
+        va.xJ = f.ptr<double>(f.o_xJ);
+        va.xW = f.ptr<double>(f.o_xW);
+        va.accumulate = accumulate;
+        prof::timed(prof::OTHER, 0.0, st, [&] { launch_vec_solve<float>(va, (int)M, st); });
+      } else {
+        VecSolveArgs<double> va;
+        va.w = f.wt;
+        va.panels = f.ptr<double>(f.o_win);
+        va.invs = f.ptr<double>(f.o_win_inv);
+        va.rhs_pt = rhs_pt;
+        va.rhsJ = rJ;
+        va.rhsW = rW;
+        va.tJ = f.ptr<double>(f.o_tJ);
+        va.tW = f.ptr<double>(f.o_tW);
+        va.xJ = f.ptr<double>(f.o_xJ);
+        va.xW = f.ptr<double>(f.o_xW);
+        va.accumulate = accumulate;
+        prof::timed(prof::OTHER, 0.0, st, [&] { launch_vec_solve<double>(va, (int)M, st); });
+      }
+      HIPCHK(hipGetLastError());
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+      HIPCHK(hipGetLastError());
+    };
+    solve(f.ptr<double>(f.o_cg), nullptr, nullptr, 0);
+    if (mixed) {
+      // one step of iterative refinement against the float64 residual covariance
+      ResidArgs ra;
+      ra.w = f.wt;
+      ra.Xs = f.ptr<double>(f.o_Xs64);
+      ra.Vt = f.ptr<double>(f.o_Vt64);
+      ra.rhs_pt = f.ptr<double>(f.o_cg);
+      ra.xJ = f.ptr<double>(f.o_xJ);
+      ra.xW = f.ptr<double>(f.o_xW);
+      ra.hJ = f.ptr<double>(f.o_hJ);
+      ra.hW = f.ptr<double>(f.o_hW);
+      ra.rJ = f.ptr<double>(f.o_rJ);
+      ra.rW = f.ptr<double>(f.o_rW);
+      ra.d = (int)d;
+      ra.sp = (int)sp;
+      ra.sf2 = f.sf2;
+      ra.sn2 = f.sn2;
+      int maxTw = 0;
+      for (int64_t m = 0; m < M; ++m) maxTw = std::max(maxTw, (int)f.Tm[m]);
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_resid(ra, (int)M, maxTw, st); });
+      HIPCHK(hipGetLastError());
+      solve(nullptr, f.ptr<double>(f.o_rJ), f.ptr<double>(f.o_rW), 1);
+    }
+  }
+  // ---- read back status, log-diagonals, g, y_ddot, q
+  std::vector<int32_t> hstat(f.n_status);
+  std::vector<double> hld(f.n_logdiag);
+  f.g.resize(sp);
+  f.ydd.resize(sp);
+  HIPCHK(hipMemcpyAsync(hstat.data(), status, 4 * f.n_status, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(hld.data(), logdiag, 8 * f.n_logdiag, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(f.g.data(), f.ptr<double>(f.o_g), 8 * sp, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(f.ydd.data(), f.ptr<double>(f.o_ydd), 8 * sp, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&f.qsum, f.ptr<double>(f.o_q), 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  prof::flush();
+  if (hstat[M]) {
+    g_failed = -1;
+    throw Err{LMA_E_NOT_PD, "Sigma_SS is not positive definite"};
+  }
+  for (int64_t m = 0; m < M; ++m)
+    if (hstat[m]) {
+      g_failed = m;
+      char buf[128];
+      snprintf(buf, sizeof buf, "residual covariance of the window of block %lld is not positive definite",
+               (long long)m);
+      throw Err{LMA_E_NOT_PD, buf};
+    }
+  if (hstat[M + 1]) {
+    g_failed = -2;
+    throw Err{LMA_E_NOT_PD, "Sigma_ddot_SS is not positive definite"};
+  }
+  // log-determinants (fixed summation order)
+  double ldR = 0;
+  for (int64_t m = 0; m < M; ++m)
+    for (int j = 0; j < f.Tm[m]; ++j) ldR += hld[(int64_t)m * maxTld + j];
+  double lss = 0, ldd = 0;
+  for (int j = 0; j < Ts; ++j) {
+    lss += hld[(int64_t)M * maxTld + j];
+    ldd += hld[(int64_t)(M + 1) * maxTld + j];
+  }
+  f.ld_R = 2 * ldR;
+  f.ld_ss = 2 * lss;
+  f.ld_dd = 2 * ldd;
+  double ydg = 0;
+  for (int64_t i = 0; i < sp; ++i) ydg += f.ydd[i] * f.g[i];
+  f.ydg = ydg;
+  f.lml = -0.5 * (f.qsum - ydg + f.ld_R + f.ld_dd - f.ld_ss + (double)n * std::log(2.0 * M_PI));
+  if (!std::isfinite(f.lml)) throw Err{LMA_E_NOT_PD, "non-finite log marginal likelihood"};
+  (void)keep;
+  *out = F.release();
+  return LMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// predict
+// ---------------------------------------------------------------------------
+template <typename TW>
+void predict_windows(lma_state& f, Run<TW>& run, int64_t n_u, const std::vector<int64_t>& ubp, const TW* Us,
+                     const TW* VtU, TW* Xbuf, const std::vector<int64_t>& Xoff, TW* winbase, const TW* Xs,
+                     const TW* Vt, const TW* c) {
+  for (int64_t m = 0; m < f.M; ++m) {
+    const WinGeom g = win_geom(f.bp, f.M, f.B, m);
+    const int64_t qhi = std::min(m + f.B, f.M - 1);
+    const int64_t r0 = ubp[m], nr = ubp[qhi + 1] - ubp[m];
+    if (nr <= 0) continue;
+    const int R = (int)cdiv(nr, TB);
+    run.add_problem(g.T, R, g.tw, true, (int)m);
+    // the stored factor: same descriptors as in the fit
+    add_window_jtiles<TW>(run.rt, g, winbase + f.win_off[m], Xs, Vt, c, f.d, f.sp);
+    // the run's problem-local inverse offset must point at window m's tiles
+    run.pd.back().invdiag_off = 0;
+    const int64_t ld = (int64_t)g.T * TB;
+    for (int r = 0; r < R; ++r) {
+      const int nv = (int)std::min<int64_t>(TB, nr - (int64_t)r * TB);
+      const int64_t pt = r0 + (int64_t)r * TB;
+      run.rt.push_back(make_tile<TW>(Xbuf + Xoff[m] + (int64_t)r * TB * ld, ld, VtU + pt * f.sp, Us + pt * f.d,
+                                     nullptr, nv, nv, SRC_KERNEL, 0));
+    }
+  }
+  (void)n_u;
+}
+
+}  // namespace
+
+// Inverted diagonal tiles of window m start at the sum of T_k*TB*TB over k < m.
+static int64_t win_inv_off(const lma_state& f, int64_t m) {
+  int64_t o = 0;
+  for (int64_t k = 0; k < m; ++k) o += (int64_t)f.Tm[k] * TB * TB;
+  return o;
+}
+
+template <typename TW>
+static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64_t* u_block_ptr, double* mean,
+                         double* var, hipStream_t st) {
+  const int64_t d = f.d, sp = f.sp, M = f.M;
+  const int Ts = (int)f.Ts;
+  const bool mixed = f.mixed();
+  std::vector<int64_t> ubp(u_block_ptr, u_block_ptr + M + 1);
+  // window geometry for test rows
+  std::vector<int64_t> Xoff(M, 0);
+  int64_t xel = 0;
+  for (int64_t m = 0; m < M; ++m) {
+    const int64_t qhi = std::min(m + f.B, M - 1);
+    const int64_t nr = ubp[qhi + 1] - ubp[m];
+    Xoff[m] = xel;
+    if (var) xel += nr * (int64_t)f.Tm[m] * TB;
+  }
+  const int64_t ldG = sp + TB;
+  Arena ar;
+  const int64_t o_Us64 = ar.reserve(8 * n_u * d);
+  const int64_t o_Us32 = mixed ? ar.reserve(4 * n_u * d) : -1;
+  const int64_t o_VtU64 = ar.reserve(8 * n_u * sp);
+  const int64_t o_VtU32 = mixed ? ar.reserve(4 * n_u * sp) : -1;
+  const int64_t o_X = ar.reserve((int64_t)sizeof(TW) * xel);
+  const int64_t o_G = ar.reserve(8 * n_u * ldG);
+  const int64_t o_vn = ar.reserve(8 * n_u);
+  const int64_t o_xi = ar.reserve(8 * n_u);
+  const int64_t o_ublk = ar.reserve(4 * n_u);
+  const int64_t o_uptr = ar.reserve(8 * (M + 1));
+  const int64_t o_Xoff = ar.reserve(8 * M);
+  const int64_t o_Tm = ar.reserve(4 * M);
+  const int64_t o_twm = ar.reserve(4 * M);
+  const int64_t o_stat = ar.reserve(4 * (M + 2));
+  const int64_t o_ld = ar.reserve(8 * 64);
+  // runs
+  Run<double> runS;
+  Run<TW> runW;
+  Run<double> runD;
+  std::vector<GemmTerm<TW>> terms;
+  std::vector<GemmOut> outs;
+  auto build = [&](char* base) {
+    ar.base = base;
+    runS = Run<double>();
+    runW = Run<TW>();
+    runD = Run<double>();
+    terms.clear();
+    outs.clear();
+    // S run in solve-only mode: right-hand sides are the test rows -> V_U^T
+    const int Rn = (int)cdiv(n_u, TB);
+    runS.add_problem(Ts, Rn, 0, true, -1);
+    add_s_jtiles<double>(runS.rt, f.ptr<double>(f.o_Lss), f.ptr<double>(f.o_Ss64), f.s, d, Ts);
+    for (int r = 0; r < Rn; ++r) {
+      const int nv = (int)std::min<int64_t>(TB, n_u - (int64_t)r * TB);
+      runS.rt.push_back(make_tile<double>(at<double>(ar, o_VtU64) + (int64_t)r * TB * sp, sp, nullptr,
+                                          at<double>(ar, o_Us64) + (int64_t)r * TB * d, nullptr, nv, nv, SRC_KERNEL,
+                                          0));
+    }
+    runS.schedule();
+    // window runs in solve-only mode
+    const TW* Us = mixed ? (const TW*)at<float>(ar, o_Us32) : (const TW*)at<double>(ar, o_Us64);
+    const TW* VtU = mixed ? (const TW*)at<float>(ar, o_VtU32) : (const TW*)at<double>(ar, o_VtU64);
+    const TW* Xs = mixed ? (const TW*)f.ptr<float>(f.o_Xs32) : (const TW*)f.ptr<double>(f.o_Xs64);
+    const TW* Vt = mixed ? (const TW*)f.ptr<float>(f.o_Vt32) : (const TW*)f.ptr<double>(f.o_Vt64);
+    const TW* c = mixed ? (const TW*)f.ptr<float>(f.o_c32) : (const TW*)f.ptr<double>(f.o_c64);
+    TW* winbase = reinterpret_cast<TW*>(f.ptr<char>(f.o_win));
+    if (!var) return;
+    predict_windows<TW>(f, runW, n_u, ubp, Us, VtU, at<TW>(ar, o_X), Xoff, winbase, Xs, Vt, c);
+    // point each problem at its window's inverted diagonal tiles
+    {
+      int pi = 0;
+      for (int64_t m = 0; m < M; ++m) {
+        const int64_t qhi = std::min(m + f.B, M - 1);
+        if (ubp[qhi + 1] - ubp[m] <= 0) continue;
+        runW.pd[pi++].invdiag_off = win_inv_off(f, m);
+      }
+    }
+    runW.schedule();
+    // G accumulation: for delta = 0..B, window m = q - delta contributes to test block q
+    for (int dl = 0; dl <= f.B; ++dl) {
+      for (int64_t q = dl; q < M; ++q) {
+        const int64_t m = q - dl;
+        const int64_t uq = ubp[q + 1] - ubp[q];
+        if (uq <= 0) continue;
+        const WinGeom g = win_geom(f.bp, M, f.B, m);
+        const int64_t ldx = (int64_t)g.T * TB;
+        const TW* Xm = at<TW>(ar, o_X) + Xoff[m] + (ubp[q] - ubp[m]) * ldx;
+        const TW* rhs = winbase + f.win_off[m] + jpanel_off(g.T);
+        for (int64_t t = 0; t < cdiv(uq, TB); ++t) {
+          const int rows = (int)std::min<int64_t>(TB, uq - t * TB);
+          for (int b = 0; b <= Ts; ++b) {
+            GemmOut o;
+            o.out = at<double>(ar, o_G) + (ubp[q] + t * TB) * ldG + (int64_t)b * TB;
+            o.ld = ldG;
+            o.rows = rows;
+            o.cols = TB;
+            o.accumulate = dl > 0 ? 1 : 0;
+            o.t0 = (int32_t)terms.size();
+            GemmTerm<TW> tm;
+            tm.a = Xm + t * TB * ldx;
+            tm.lda = ldx;
+            tm.anr = rows;
+            tm.b = rhs + (int64_t)b * TB * ldx;
+            tm.ldb = ldx;
+            tm.bnr = TB;
+            tm.k0 = dl == 0 ? 0 : g.tw * TB;
+            tm.k1 = g.T * TB;
+            terms.push_back(tm);
+            o.t1 = (int32_t)terms.size();
+            outs.push_back(o);
+          }
+        }
+      }
+    }
+    // Sigma_ddot run in solve-only mode: right-hand sides E_u = k_u - G_u (in place)
+    const int Ru = (int)cdiv(n_u, TB);
+    runD.add_problem(Ts, Ru, 0, true, -2);
+    for (int i = 0; i < Ts; ++i) {
+      const int nv = (int)std::min<int64_t>(TB, f.s - (int64_t)i * TB);
+      RowTile<double> r = make_tile<double>(f.ptr<double>(f.o_Ldd) + jpanel_off(i), (int64_t)(i + 1) * TB, nullptr,
+                                            nullptr, nullptr, nv, TB, SRC_EXPLICIT, 1);
+      r.expl = f.ptr<double>(f.o_Sdd) + (int64_t)i * TB * sp;
+      r.eld = sp;
+      runD.rt.push_back(r);
+    }
+    for (int r = 0; r < Ru; ++r) {
+      const int nv = (int)std::min<int64_t>(TB, n_u - (int64_t)r * TB);
+      double* rows = at<double>(ar, o_G) + (int64_t)r * TB * ldG;
+      RowTile<double> t = make_tile<double>(rows, ldG, nullptr, nullptr, nullptr, nv, nv, SRC_EXPLICIT, 0);
+      t.expl = rows;
+      t.eld = ldG;
+      runD.rt.push_back(t);
+    }
+    runD.schedule();
+  };
+  build(nullptr);
+  // dG outputs: one launch per delta; record split points
+  std::vector<int> dl_split(f.B + 2, 0);
+  {
+    int idx = 0;
+    for (int dl = 0; dl <= f.B; ++dl) {
+      dl_split[dl] = idx;
+      for (int64_t q = dl; q < M; ++q) {
+        const int64_t uq = ubp[q + 1] - ubp[q];
+        if (uq <= 0) continue;
+        idx += (int)cdiv(uq, TB) * (Ts + 1);
+      }
+    }
+    dl_split[f.B + 1] = idx;
+  }
+  const int64_t o_meta = ar.reserve(runS.meta_bytes() + runW.meta_bytes() + runD.meta_bytes());
+  const int64_t o_terms = ar.reserve(sizeof(GemmTerm<TW>) * std::max<size_t>(terms.size(), 1));
+  const int64_t o_outs = ar.reserve(sizeof(GemmOut) * std::max<size_t>(outs.size(), 1));
+  ar.cap = ar.used;
+  void* mem = nullptr;
+  if (hipMalloc(&mem, (size_t)ar.cap) != hipSuccess || !mem) {
+    (void)hipGetLastError();
+    throw Err{LMA_E_NOMEM, "hipMalloc of the prediction workspace failed"};
+  }
+  struct Guard {
+    void* p;
+    hipStream_t s;
+    ~Guard() {
+      if (p) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(p);
+      }
+    }
+  } guard{mem, st};
+  build(reinterpret_cast<char*>(mem));
+  {
+    char* mp = at<char>(ar, o_meta);
+    runS.upload(mp, st);
+    mp += runS.meta_bytes();
+    runW.upload(mp, st);
+    mp += runW.meta_bytes();
+    runD.upload(mp, st);
+    if (!terms.empty())
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_terms), terms.data(), sizeof(GemmTerm<TW>) * terms.size(),
+                            hipMemcpyHostToDevice, st));
+    if (!outs.empty())
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_outs), outs.data(), sizeof(GemmOut) * outs.size(), hipMemcpyHostToDevice,
+                            st));
+  }
+  std::vector<int32_t> ublk(n_u);
+  for (int64_t q = 0; q < M; ++q)
+    for (int64_t u = ubp[q]; u < ubp[q + 1]; ++u) ublk[u] = (int32_t)q;
+  std::vector<int64_t> Xoff_h(Xoff);
+  HIPCHK(hipMemcpyAsync(at<char>(ar, o_ublk), ublk.data(), 4 * n_u, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(at<char>(ar, o_uptr), ubp.data(), 8 * (M + 1), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(at<char>(ar, o_Xoff), Xoff_h.data(), 8 * M, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(at<char>(ar, o_Tm), f.Tm.data(), 4 * M, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(at<char>(ar, o_twm), f.twm.data(), 4 * M, hipMemcpyHostToDevice, st));
+  int32_t* stat = at<int32_t>(ar, o_stat);
+  double* ldg = at<double>(ar, o_ld);
+  HIPCHK(hipMemsetAsync(stat, 0, 4 * (M + 2), st));
+  // scale test inputs
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(U, n_u, (int)d, f.ie, at<double>(ar, o_Us64), mixed ? at<float>(ar, o_Us32) : nullptr, st); });
+  HIPCHK(hipGetLastError());
+  auto exec = [&](auto& run, auto* invdiag, int vlen) {
+    using TT = typename std::remove_pointer<decltype(invdiag)>::type;
+    StepArgs<TT> a;
+    a.rt = run.d_rt;
+    a.pd = run.d_pd;
+    a.vlen = vlen;
+    a.vld = sp;
+    a.d = (int)d;
+    a.sf2 = f.sf2;
+    a.sn2 = f.sn2;
+    a.invdiag = invdiag;
+    a.logdiag = ldg;
+    a.status = stat;
+    a.maxT = 0;
+    for (int j = 0; j < run.maxT; ++j) {
+      a.j = j;
+      a.items = run.d_items + run.upd_off[j];
+      a.nitems = (int32_t)run.upd_n[j];
+      prof::timed(prof::UPDATE, prof::on ? run.update_flops(j, vlen > 0 ? f.s : 0) : 0.0, st,
+                  [&] { launch_update<TT>(a, st); });
+      HIPCHK(hipGetLastError());
+      a.items = run.d_items + run.trs_off[j];
+      a.nitems = (int32_t)run.trs_n[j];
+      prof::timed(prof::TRSM, 0.0, st, [&] { launch_trsm<TT>(a, st); });
+      HIPCHK(hipGetLastError());
+    }
+  };
+  exec(runS, f.ptr<double>(f.o_Lss_inv), 0);
+  {
+    MeanArgs ma;
+    ma.w = f.wt;
+    ma.n_u = n_u;
+    ma.B = (int)f.B;
+    ma.d = (int)d;
+    ma.s = (int)f.s;
+    ma.sp = (int)sp;
+    ma.ublk = at<int32_t>(ar, o_ublk);
+    ma.Us = at<double>(ar, o_Us64);
+    ma.Ss = f.ptr<double>(f.o_Ss64);
+    ma.Xs = f.ptr<double>(f.o_Xs64);
+    ma.VtU = at<double>(ar, o_VtU64);
+    ma.g = f.ptr<double>(f.o_g);
+    ma.xJ = f.ptr<double>(f.o_xJ);
+    ma.xW = f.ptr<double>(f.o_xW);
+    ma.hJ = f.ptr<double>(f.o_hJ);
+    ma.hW = f.ptr<double>(f.o_hW);
+    ma.mu = f.mu;
+    ma.sf2 = f.sf2;
+    ma.mean = mean;
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_mean(ma, st); });
+    HIPCHK(hipGetLastError());
+  }
+  if (!var) {
+    HIPCHK(hipStreamSynchronize(st));
+    prof::flush();
+    return;
+  }
+  if (mixed) launch_cast(at<double>(ar, o_VtU64), at<float>(ar, o_VtU32), n_u * sp, st);
+  exec(runW, reinterpret_cast<TW*>(f.ptr<char>(f.o_win_inv)), (int)sp);
+  for (int dl = 0; dl <= f.B; ++dl) {
+    const int a0 = dl_split[dl], a1 = dl_split[dl + 1];
+    if (a1 > a0)
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_tile_gemm<TW>(at<GemmTerm<TW>>(ar, o_terms), at<GemmOut>(ar, o_outs) + a0, a1 - a0, st); });
+    HIPCHK(hipGetLastError());
+  }
+  {
+    XiArgs<TW> xa;
+    xa.n_u = n_u;
+    xa.B = (int)f.B;
+    xa.ublk = at<int32_t>(ar, o_ublk);
+    xa.uptr = at<int64_t>(ar, o_uptr);
+    xa.Xoff = at<int64_t>(ar, o_Xoff);
+    xa.Tm = at<int32_t>(ar, o_Tm);
+    xa.twm = at<int32_t>(ar, o_twm);
+    xa.Xbuf = at<TW>(ar, o_X);
+    xa.xi = at<double>(ar, o_xi);
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_pred_xi<TW>(xa, st); });
+    HIPCHK(hipGetLastError());
+  }
+  PredArgs pa;
+  pa.n_u = n_u;
+  pa.sp = (int)sp;
+  pa.s = (int)f.s;
+  pa.d = (int)d;
+  pa.G = at<double>(ar, o_G);
+  pa.ldG = ldG;
+  pa.Us = at<double>(ar, o_Us64);
+  pa.Ss = f.ptr<double>(f.o_Ss64);
+  pa.VtU = at<double>(ar, o_VtU64);
+  pa.g = f.ptr<double>(f.o_g);
+  pa.mu = f.mu;
+  pa.sf2 = f.sf2;
+  pa.sn2 = f.sn2;
+  pa.mean = nullptr;
+  pa.var = var;
+  pa.vn = at<double>(ar, o_vn);
+  pa.xi = at<double>(ar, o_xi);
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_pred_E(pa, st); });
+  HIPCHK(hipGetLastError());
+  exec(runD, f.ptr<double>(f.o_Ldd_inv), 0);
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_pred_var(pa, st); });
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));
+  prof::flush();
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+lma_status lma_fit(const lma_problem* p, hipStream_t stream, lma_state** out) {
+  g_err.clear();
+  if (!out) {
+    g_err = "out is NULL";
+    return LMA_E_ARG;
+  }
+  *out = nullptr;
+  try {
+    return do_fit(p, stream, out, true);
+  } catch (const Err& e) {
+    set_err(e);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return LMA_E_NOMEM;
+  }
+}
+
+lma_status lma_predict(lma_state* f, int64_t n_u, const double* U, const int64_t* u_block_ptr, double* mean,
+                       double* var, hipStream_t stream) {
+  g_err.clear();
+  try {
+    if (!f) throw Err{LMA_E_ARG, "state is NULL"};
+    if (n_u < 0) throw Err{LMA_E_ARG, "n_u < 0"};
+    if (n_u == 0) return LMA_OK;
+    if (!U || !u_block_ptr || !mean) throw Err{LMA_E_ARG, "NULL array"};
+    if (u_block_ptr[0] != 0 || u_block_ptr[f->M] != n_u)
+      throw Err{LMA_E_ARG, "u_block_ptr must start at 0 and end at n_u"};
+    for (int64_t m = 0; m < f->M; ++m)
+      if (u_block_ptr[m + 1] < u_block_ptr[m]) throw Err{LMA_E_ARG, "u_block_ptr must be non-decreasing"};
+    if (f->mixed())
+      predict_impl<float>(*f, n_u, U, u_block_ptr, mean, var, stream);
+    else
+      predict_impl<double>(*f, n_u, U, u_block_ptr, mean, var, stream);
+    return LMA_OK;
+  } catch (const Err& e) {
+    set_err(e);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return LMA_E_NOMEM;
+  }
+}
+
+lma_status lma_lml(const lma_problem* p, double* lml, double* grad, hipStream_t stream) {
+  g_err.clear();
+  if (!lml) {
+    g_err = "lml is NULL";
+    return LMA_E_ARG;
+  }
+  if (grad) {
+    g_err = "gradient is not available in this build";
+    return LMA_E_ARG;
+  }
+  lma_state* f = nullptr;
+  lma_status s = lma_fit(p, stream, &f);
+  if (s != LMA_OK) return s;
+  *lml = f->lml;
+  delete f;
+  return LMA_OK;
+}
+
+lma_status lma_state_lml(const lma_state* f, double* lml) {
+  if (!f || !lml) {
+    g_err = "NULL argument";
+    return LMA_E_ARG;
+  }
+  *lml = f->lml;
+  return LMA_OK;
+}
+
+void lma_free(lma_state* f) { delete f; }
+
+const char* lma_last_error(void) { return g_err.c_str(); }
+
+int64_t lma_failed_block(void) { return g_failed; }
+
+const char* lma_version(void) { return "lma-gfx950 0.1"; }
+
+void lma_profile_enable(int on) { prof::on = on != 0; }
+
+lma_status lma_profile_read(lma_profile* out, int reset) {
+  if (!out) {
+    g_err = "out is NULL";
+    return LMA_E_ARG;
+  }
+  *out = prof::acc;
+  if (reset) prof::acc = lma_profile{};
+  return LMA_OK;
+}
+
+}  // extern "C"

@@ -233,7 +233,11 @@ def kmeans_partition(rng, X, M, lo, hi, iters=20, U=None):
     Returns (perm, block_ptr, uperm, u_block_ptr): X[perm] is block-contiguous,
     U[uperm] is block-contiguous with test points assigned to the nearest
     block centre."""
-    C = _lloyd(X, _kmeanspp(rng, X, M), iters)
+    n = X.shape[0]
+    # centres from subsamples (k-means++ seeding, then Lloyd), assignment of all points
+    sub_pp = X[np.sort(rng.choice(n, size=min(n, 64 * M), replace=False))] if n > 64 * M else X
+    sub_ll = X[np.sort(rng.choice(n, size=min(n, 512 * M), replace=False))] if n > 512 * M else X
+    C = _lloyd(sub_ll, _kmeanspp(rng, sub_pp, M), iters)
     lab = _capacity_assign(_sqdist(X, C), lo, hi)
     cnt = np.bincount(lab, minlength=M)
     Cf = np.zeros_like(C)
@@ -378,7 +382,7 @@ def make_config3(F=4096):
     return make_uniform_kmeans(3, 131072, 8, 128, 2, 512, 0, 0.05, F=F, name="cfg3")
 
 
-def make_config2(F=2048, n=524288, M=256, n_u=65536, s=1024, B=3, sn2_model=0.01,
+def make_config2(F=512, n=524288, M=256, n_u=65536, s=1024, B=3, sn2_model=0.01,
                  lo=1024, hi=3072, kmeans_iters=10):
     """n=524288 in 21-D drawn from an equal-weight mixture of 32 Gaussians
     (centres ~ U[0,1]^21, spread N(0, 0.2^2 I)); outputs = smooth RFF draw

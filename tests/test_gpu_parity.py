@@ -1,0 +1,114 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bars: float64 mode, relative 2-norm error <= 1e-9 per output vector (mean,
+variance) and relative error <= 1e-9 on the log marginal likelihood; mixed
+mode <= 1e-4 on the same measures."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lma as olma
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "mixed": 1e-4}
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def gpu_fit_predict(lib, p, precision):
+    st = lib.fit_problem(p, precision=precision)
+    mean, var = st.predict(p.U, p.u_block_ptr)
+    out = mean.cpu().numpy(), var.cpu().numpy(), st.lml()
+    st.free()
+    return out
+
+
+def check(lib, p, precision, ref=None):
+    print(f"case {p.name} n={p.n} d={p.d} M={p.M} s={p.s} B={p.B} n_u={p.n_u} {precision}", flush=True)
+    ref = ref or olma.fit_predict(p)
+    m, v, l = gpu_fit_predict(lib, p, precision)
+    em, ev, el = rel(m, ref["mean"]), rel(v, ref["var"]), abs(l - ref["lml"]) / abs(ref["lml"])
+    print(f"  rel err mean {em:.2e} var {ev:.2e} lml {el:.2e}", flush=True)
+    tol = TOL[precision]
+    assert em <= tol and ev <= tol and el <= tol
+    assert np.all(np.isfinite(m)) and np.all(np.isfinite(v))
+    return em, ev, el
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("B", [0, 1, 2, 5])
+def test_tiny_uneven_blocks_every_order(lib, B, precision):
+    """Blocks of 17-40 points (one partial tile each), an empty test block, and
+    B from PIC (0) to the full GP (M-1 = 5)."""
+    p = synth.make_random(seed=3, n=180, d=2, M=6, s=12, n_u=40, B=B, empty_test_block=2,
+                          prior_mean=0.3, name="tiny")
+    check(lib, p, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("B", [1, 3])
+def test_several_tiles_ragged(lib, B, precision):
+    """Blocks of 200-700 points, |S| = 200 (two tiles, ragged), d = 5: windows
+    span several 128-row tiles with ragged tails in W_m and D_m."""
+    p = synth.make_random(seed=11, n=3000, d=5, M=7, s=200, n_u=600, B=B, uneven=(200, 700),
+                          ell_range=(0.3, 1.5), sn2=0.02, name="ragged")
+    check(lib, p, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_config0(lib, precision):
+    """n=2048, d=4, M=8 blocks of 256, B=1, |S|=64, 256 test points."""
+    check(lib, synth.make_config(0), precision)
+
+
+def test_fp64_is_deterministic(lib):
+    p = synth.make_random(seed=5, n=900, d=3, M=5, s=70, n_u=100, B=2, uneven=(100, 250))
+    a = gpu_fit_predict(lib, p, "fp64")
+    b = gpu_fit_predict(lib, p, "fp64")
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_lml_entry_point(lib):
+    p = synth.make_random(seed=7, n=500, d=3, M=4, s=40, n_u=0, B=1, uneven=(80, 160))
+    ref = olma.lml(p)
+    val = lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean)
+    assert abs(val - ref) <= 1e-9 * abs(ref)
+
+
+def test_bad_partition_is_rejected(lib):
+    p = synth.make_random(seed=7, n=200, d=2, M=4, s=10, n_u=0, B=1)
+    bad = p.block_ptr.copy()
+    bad[2] = bad[1]
+    with pytest.raises(lib.LmaError) as e:
+        lib.fit(p.X, p.y, bad, p.S, p.B, p.log_hyp)
+    assert e.value.status == lib.LMA_E_ARG
+
+
+def test_non_pd_window_reports_its_block(lib):
+    """A NaN input makes the residual covariance of the windows that hold it
+    non positive definite; the error names a block whose window holds it and
+    no NaN result is returned."""
+    p = synth.make_random(seed=9, n=400, d=2, M=5, s=16, n_u=0, B=1, uneven=(60, 100))
+    X = p.X.copy()
+    k = 3
+    X[p.block_ptr[k] + 2, 0] = np.nan
+    S = p.S.copy()
+    # keep the NaN out of the support set
+    S[:] = np.nan_to_num(S)
+    with pytest.raises(lib.LmaError) as e:
+        lib.fit(X, p.y, p.block_ptr, S, p.B, p.log_hyp)
+    assert e.value.status == lib.LMA_E_NOT_PD
+    assert k - p.B <= e.value.block <= k
+
+
+def test_non_pd_support_covariance(lib):
+    p = synth.make_random(seed=9, n=400, d=2, M=5, s=16, n_u=0, B=1, uneven=(60, 100))
+    S = p.S.copy()
+    S[3, 1] = np.nan
+    with pytest.raises(lib.LmaError) as e:
+        lib.fit(p.X, p.y, p.block_ptr, S, p.B, p.log_hyp)
+    assert e.value.status == lib.LMA_E_NOT_PD and e.value.block == -1
