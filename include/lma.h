@@ -137,6 +137,7 @@ typedef struct {
   double trsm_ms;            /* off-diagonal triangular-solve launches */
   double other_ms;           /* every other kernel of the library */
   double update_alg_flops;   /* algorithmic flops of the timed update launches */
+  double update_alg_flops_f64; /* the part of them done on float64 matrix cores */
   int64_t update_launches;
   int64_t other_launches;
 } lma_profile;

@@ -51,7 +51,7 @@ class Profile(ctypes.Structure):
     _fields_ = [
         ("update_ms", ctypes.c_double), ("diag_ms", ctypes.c_double),
         ("trsm_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
-        ("update_alg_flops", ctypes.c_double),
+        ("update_alg_flops", ctypes.c_double), ("update_alg_flops_f64", ctypes.c_double),
         ("update_launches", ctypes.c_int64), ("other_launches", ctypes.c_int64),
     ]
 

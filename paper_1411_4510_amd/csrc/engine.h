@@ -36,6 +36,8 @@ struct RowTile {
   int64_t ld;
   const T* vt;       // whitened support rows of the tile's points (row r at vt + r*vld) or null
   const T* xs;       // length-scaled coordinates of the tile's points ([r][d]) or null
+  const double* vt64;  // float64 copies used by the mixed-precision update (V part and
+  const double* xs64;  // covariance tile in float64); equal to vt / xs in float64 runs
   const T* cv;       // centred outputs y - mu of the tile's points (column side of SRC_CVEC)
   const T* expl;     // explicit entries: row r, global column c at expl[r*eld + c]
   int64_t eld;
@@ -76,8 +78,11 @@ struct StepArgs {
 };
 
 // Host-side launchers (engine.hip).
+// mixed = true (float storage only): the covariance tile and the V_i V_j^T
+// correction are formed in float64 (float64 MFMA), the factor updates in
+// float32; the tile is rounded to float32 once, after the cancellation.
 template <typename T>
-void launch_update(const StepArgs<T>& a, hipStream_t st);
+void launch_update(const StepArgs<T>& a, bool mixed, hipStream_t st);
 template <typename T>
 void launch_diag(const StepArgs<T>& a, const int32_t* plist, int np, hipStream_t st);
 template <typename T>

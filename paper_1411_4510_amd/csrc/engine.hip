@@ -10,6 +10,8 @@
 // current one runs on the matrix cores.
 #include "engine.h"
 
+#include <type_traits>
+
 namespace lma {
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
@@ -57,7 +59,9 @@ __device__ inline int xcd_logical(int bid, int nb) {
 }
 
 // acc[ra][rb] += A[arow0 + 16 ra + i, k] * Bm[brow0 + 16 rb + j, k] over k in [k0, k1).
-template <typename Tin, typename Tc>
+// PERMA feeds the A rows of each 16-row sub-tile in the order r(4a+b) = a+4b, which
+// turns the float32 16x16 output layout into the float64 one (row l/16 + 4v).
+template <typename Tin, typename Tc, bool PERMA = false>
 __device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
                                           const Tin* __restrict__ A, int64_t lda, int anr,
                                           const Tin* __restrict__ Bm, int64_t ldb, int bnr,
@@ -69,7 +73,7 @@ __device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
   bool va[4], vb[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int ra = arow0 + t * 16 + r16;
+    const int ra = arow0 + t * 16 + (PERMA ? ((r16 >> 2) | ((r16 & 3) << 2)) : r16);
     va[t] = ra < anr;
     pa[t] = A + (int64_t)(va[t] ? ra : 0) * lda + k0 + kq;
     const int rb = brow0 + t * 16 + r16;
@@ -126,8 +130,10 @@ __device__ inline void zero_acc(typename Mfma<Tc>::acc (&acc)[4][4]) {
 // ---------------------------------------------------------------------------
 // update: C_ij = K_ij - V_i V_j^T - sum_{k<j} L_ik L_jk^T for every item (p, i)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool MIXED>
 __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
+  // covariance tile and V-part precision: float64 when T is double or MIXED
+  typedef typename std::conditional<MIXED, double, T>::type TK;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int logical = xcd_logical(blockIdx.x, gridDim.x);
   if (logical >= a.nitems) return;
@@ -137,29 +143,39 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
   const RowTile<T> rj = a.rt[pd.first + a.j];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
 
-  typename Mfma<T>::acc acc[4][4];
-  zero_acc<T>(acc);
-  if (ri.vt != nullptr && rj.vt != nullptr && a.vlen > 0)
-    wave_gemm<T, T>(acc, ri.vt, a.vld, ri.nvalid, rj.vt, a.vld, rj.nvalid, 0, a.vlen, wr * 64, wc * 64,
-                    lane);
-  if (a.j > 0)
-    wave_gemm<T, T>(acc, ri.panel, ri.ld, ri.nstore, rj.panel, rj.ld, rj.nstore, 0, a.j * TB, wr * 64,
-                    wc * 64, lane);
+  typename Mfma<TK>::acc accv[4][4];   // V_i V_j^T
+  typename Mfma<T>::acc accl[4][4];    // sum_k L_ik L_jk^T (aliases accv when not MIXED)
+  zero_acc<TK>(accv);
+  if constexpr (MIXED) zero_acc<T>(accl);
+  const TK* vi = MIXED ? (const TK*)ri.vt64 : (const TK*)ri.vt;
+  const TK* vj = MIXED ? (const TK*)rj.vt64 : (const TK*)rj.vt;
+  if (vi != nullptr && vj != nullptr && a.vlen > 0)
+    wave_gemm<TK, TK>(accv, vi, a.vld, ri.nvalid, vj, a.vld, rj.nvalid, 0, a.vlen, wr * 64, wc * 64, lane);
+  if (a.j > 0) {
+    if constexpr (MIXED)
+      wave_gemm<T, T, true>(accl, ri.panel, ri.ld, ri.nstore, rj.panel, rj.ld, rj.nstore, 0, a.j * TB, wr * 64,
+                            wc * 64, lane);
+    else
+      wave_gemm<T, T>(accv, ri.panel, ri.ld, ri.nstore, rj.panel, rj.ld, rj.nstore, 0, a.j * TB, wr * 64, wc * 64,
+                      lane);
+  }
 
   const int d = a.d;
-  T* xr = reinterpret_cast<T*>(smem_raw);  // [d][TB] row-side coordinates
-  T* xc = xr + d * TB;                     // [d][TB] column-side coordinates
+  TK* xr = reinterpret_cast<TK*>(smem_raw);  // [d][TB] row-side coordinates
+  TK* xc = xr + d * TB;                      // [d][TB] column-side coordinates
   const bool kern = ri.src == SRC_KERNEL;
   if (kern) {
+    const TK* xsi = MIXED ? (const TK*)ri.xs64 : (const TK*)ri.xs;
+    const TK* xsj = MIXED ? (const TK*)rj.xs64 : (const TK*)rj.xs;
     for (int idx = tid; idx < TB * d; idx += NT) {
       const int r = idx / d, t = idx - r * d;
-      xr[t * TB + r] = r < ri.nvalid ? ri.xs[(int64_t)r * d + t] : T(0);
-      xc[t * TB + r] = r < rj.nvalid ? rj.xs[(int64_t)r * d + t] : T(0);
+      xr[t * TB + r] = r < ri.nvalid ? xsi[(int64_t)r * d + t] : TK(0);
+      xc[t * TB + r] = r < rj.nvalid ? xsj[(int64_t)r * d + t] : TK(0);
     }
   }
   __syncthreads();
   const bool diag = ri.is_j && (it.tile == a.j);
-  const T sf2 = (T)a.sf2, sn2 = (T)a.sn2;
+  const TK sf2 = (TK)a.sf2, sn2 = (TK)a.sn2;
   T* out = ri.panel + (int64_t)a.j * TB;
 #pragma unroll
   for (int rs = 0; rs < 4; ++rs) {
@@ -167,27 +183,32 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
     for (int cs = 0; cs < 4; ++cs) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = wr * 64 + rs * 16 + Mfma<T>::row(lane, v);
+        const int row = wr * 64 + rs * 16 + Mfma<TK>::row(lane, v);
         const int col = wc * 64 + cs * 16 + (lane & 15);
-        T kv = T(0);
+        TK kv = TK(0);
         if (row < ri.nvalid && col < rj.nvalid) {
           if (kern) {
-            T s = T(0);
+            TK s = TK(0);
             for (int t = 0; t < d; ++t) {
-              const T df = xr[t * TB + row] - xc[t * TB + col];
+              const TK df = xr[t * TB + row] - xc[t * TB + col];
               s += df * df;
             }
-            kv = sf2 * k_exp(T(-0.5) * s);
+            kv = sf2 * k_exp(TK(-0.5) * s);
             if (diag && row == col) kv += sn2;
           } else if (ri.src == SRC_EXPLICIT) {
-            kv = ri.expl[(int64_t)row * ri.eld + (int64_t)a.j * TB + col];
+            kv = (TK)ri.expl[(int64_t)row * ri.eld + (int64_t)a.j * TB + col];
           } else {
-            kv = row == 0 ? rj.cv[col] : T(0);
+            kv = row == 0 ? (TK)rj.cv[col] : TK(0);
           }
         } else if (diag && row == col) {
-          kv = T(1);
+          kv = TK(1);
         }
-        if (row < ri.nstore) out[(int64_t)row * ri.ld + col] = kv - acc[rs][cs][v];
+        T val;
+        if constexpr (MIXED)
+          val = (T)(kv - accv[rs][cs][v]) - accl[rs][cs][v];
+        else
+          val = (T)(kv - accv[rs][cs][v]);
+        if (row < ri.nstore) out[(int64_t)row * ri.ld + col] = val;
       }
     }
   }
@@ -357,10 +378,19 @@ size_t diag_lds_bytes() {
 }
 
 template <typename T>
-void launch_update(const StepArgs<T>& a, hipStream_t st) {
+void launch_update(const StepArgs<T>& a, bool mixed, hipStream_t st) {
   if (a.nitems <= 0) return;
-  const size_t lds = 2 * (size_t)a.d * TB * sizeof(T);
-  hipLaunchKernelGGL(k_update<T>, dim3(pad8(a.nitems)), dim3(NT), lds, st, a);
+  if constexpr (std::is_same<T, float>::value) {
+    if (mixed) {
+      const size_t lds = 2 * (size_t)a.d * TB * sizeof(double);
+      hipLaunchKernelGGL((k_update<T, true>), dim3(pad8(a.nitems)), dim3(NT), lds, st, a);
+      return;
+    }
+  }
+  {
+    const size_t lds = 2 * (size_t)a.d * TB * sizeof(T);
+    hipLaunchKernelGGL((k_update<T, false>), dim3(pad8(a.nitems)), dim3(NT), lds, st, a);
+  }
 }
 
 template <typename T>
@@ -389,15 +419,18 @@ hipError_t engine_init() {
   e = hipFuncSetAttribute((const void*)k_diag<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)diag_lds_bytes<float>());
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_update<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  e = hipFuncSetAttribute((const void*)k_update<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(2 * 64 * TB * sizeof(double)));
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_update<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  e = hipFuncSetAttribute((const void*)k_update<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(2 * 64 * TB * sizeof(double)));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_update<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)(2 * 64 * TB * sizeof(float)));
 }
 
-template void launch_update<double>(const StepArgs<double>&, hipStream_t);
-template void launch_update<float>(const StepArgs<float>&, hipStream_t);
+template void launch_update<double>(const StepArgs<double>&, bool, hipStream_t);
+template void launch_update<float>(const StepArgs<float>&, bool, hipStream_t);
 template void launch_diag<double>(const StepArgs<double>&, const int32_t*, int, hipStream_t);
 template void launch_diag<float>(const StepArgs<float>&, const int32_t*, int, hipStream_t);
 template void launch_trsm<double>(const StepArgs<double>&, hipStream_t);

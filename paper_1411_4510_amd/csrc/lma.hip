@@ -85,7 +85,7 @@ bool on = false;
 struct Rec {
   int kind;
   hipEvent_t a, b;
-  double flops;
+  double flops, flops64;
 };
 std::vector<Rec> pending;
 std::vector<hipEvent_t> pool;
@@ -101,12 +101,12 @@ hipEvent_t get() {
   return e;
 }
 template <class F>
-void timed(int kind, double flops, hipStream_t st, F&& launch) {
+void timed(int kind, double flops, hipStream_t st, F&& launch, double flops64 = 0.0) {
   if (!on) {
     launch();
     return;
   }
-  Rec r{kind, get(), get(), flops};
+  Rec r{kind, get(), get(), flops, flops64};
   HIPCHK(hipEventRecord(r.a, st));
   launch();
   HIPCHK(hipEventRecord(r.b, st));
@@ -121,6 +121,7 @@ void flush() {
       case UPDATE:
         acc.update_ms += ms;
         acc.update_alg_flops += r.flops;
+        acc.update_alg_flops_f64 += r.flops64;
         acc.update_launches += 1;
         break;
       case DIAG: acc.diag_ms += ms; break;
@@ -202,20 +203,25 @@ struct Run {
     }
   }
 
-  // multiply-adds (x2) of the update launch of step j on real entries only
-  double update_flops(int j, int64_t s_valid) const {
-    double f = 0.0;
+  // multiply-adds (x2) of the update launch of step j on real entries only;
+  // f64 receives the part done in float64 (all of it for double runs, the V
+  // part in mixed runs)
+  double update_flops(int j, int64_t s_valid, double* f64) const {
+    double f = 0.0, fv = 0.0;
     for (int64_t t = upd_off[j]; t < upd_off[j] + upd_n[j]; ++t) {
       const WorkItem it = items[t];
       const ProbDesc& p = pd[it.p];
       const RowTile<T>& ri = rt[p.first + it.tile];
       const RowTile<T>& rj = rt[p.first + j];
-      double K = (ri.vt && rj.vt) ? (double)s_valid : 0.0;
+      const double Kv = (ri.vt64 && rj.vt64) ? (double)s_valid : 0.0;
+      double K = Kv;
       for (int k = 0; k < j; ++k) K += rt[p.first + k].nvalid;
       const double rows = ri.nvalid, cols = rj.nvalid;
       const double pairs = (ri.is_j && it.tile == j) ? rows * (rows + 1) / 2 : rows * cols;
       f += 2.0 * pairs * K;
+      fv += 2.0 * pairs * Kv;
     }
+    *f64 = std::is_same<T, double>::value ? f : fv;
     return f;
   }
 
@@ -244,34 +250,6 @@ struct Run {
       HIPCHK(hipMemcpyAsync(p, plist.data(), sizeof(int32_t) * plist.size(), hipMemcpyHostToDevice, st));
   }
 
-  void execute(T* invdiag, double* logdiag, int32_t* status, int vlen, int64_t vld, int d, double sf2,
-               double sn2, hipStream_t st) {
-    StepArgs<T> a;
-    a.rt = d_rt;
-    a.pd = d_pd;
-    a.vlen = vlen;
-    a.vld = vld;
-    a.d = d;
-    a.sf2 = sf2;
-    a.sn2 = sn2;
-    a.invdiag = invdiag;
-    a.logdiag = logdiag;
-    a.status = status;
-    a.maxT = maxT;
-    for (int j = 0; j < maxT; ++j) {
-      a.j = j;
-      a.items = d_items + upd_off[j];
-      a.nitems = (int32_t)upd_n[j];
-      launch_update<T>(a, st);
-      HIPCHK(hipGetLastError());
-      launch_diag<T>(a, d_plist + pl_off[j], (int)pl_n[j], st);
-      HIPCHK(hipGetLastError());
-      a.items = d_items + trs_off[j];
-      a.nitems = (int32_t)trs_n[j];
-      launch_trsm<T>(a, st);
-      HIPCHK(hipGetLastError());
-    }
-  }
 };
 
 }  // namespace
@@ -288,13 +266,13 @@ struct lma_state {
   std::vector<int64_t> bp;
   Arena ar;
   // offsets in the arena
-  int64_t o_Xs64 = -1, o_Xs32 = -1, o_Ss64 = -1, o_Ss32 = -1, o_c64 = -1, o_c32 = -1;
-  int64_t o_Vt64 = -1, o_Vt32 = -1, o_Lss = -1, o_Lss_inv = -1;
+  int64_t o_Xs64 = -1, o_Ss64 = -1, o_c64 = -1, o_c32 = -1;
+  int64_t o_Vt64 = -1, o_Lss = -1, o_Lss_inv = -1;
   int64_t o_win = -1, o_win_inv = -1, o_partial = -1, o_Sdd = -1, o_ydd = -1, o_q = -1;
   int64_t o_Ldd = -1, o_Ldd_inv = -1, o_g = -1, o_logdiag = -1, o_status = -1, o_meta = -1;
   int64_t n_logdiag = 0, n_status = 0;
   // mean path: window table, beta vectors and their V-projections
-  int64_t o_wt = -1, o_xJ = -1, o_xW = -1, o_tJ = -1, o_tW = -1, o_rJ = -1, o_rW = -1, o_hJ = -1, o_hW = -1,
+  int64_t o_wt = -1, o_xJ = -1, o_xW = -1, o_tJ = -1, o_tW = -1, o_hJ = -1, o_hW = -1,
           o_cg = -1, vec_elems = 0;
   WinTab wt;
   // window geometry
@@ -367,6 +345,8 @@ RowTile<T> make_tile(T* panel, int64_t ld, const T* vt, const T* xs, const T* cv
   r.nstore = nstore;
   r.src = src;
   r.is_j = is_j;
+  r.vt64 = std::is_same<T, double>::value ? reinterpret_cast<const double*>(vt) : nullptr;
+  r.xs64 = std::is_same<T, double>::value ? reinterpret_cast<const double*>(xs) : nullptr;
   return r;
 }
 
@@ -389,8 +369,10 @@ WinGeom win_geom(const std::vector<int64_t>& bp, int64_t M, int64_t B, int64_t m
 }
 
 // J row tiles of window m (descriptors shared by fit and predict runs).
+// Covariance tiles and the V part always read the float64 coordinates and V rows
+// (float runs use them through vt64 / xs64 in the mixed update kernel).
 template <typename T>
-void add_window_jtiles(std::vector<RowTile<T>>& rt, const WinGeom& g, T* base, const T* Xs, const T* Vt,
+void add_window_jtiles(std::vector<RowTile<T>>& rt, const WinGeom& g, T* base, const double* Xs, const double* Vt,
                        const T* c, int64_t d, int64_t sp) {
   for (int i = 0; i < g.T; ++i) {
     int64_t pt;
@@ -402,8 +384,13 @@ void add_window_jtiles(std::vector<RowTile<T>>& rt, const WinGeom& g, T* base, c
       pt = g.dstart + (int64_t)(i - g.tw) * TB;
       nv = (int)std::min<int64_t>(TB, g.b - (int64_t)(i - g.tw) * TB);
     }
-    rt.push_back(make_tile<T>(base + jpanel_off(i), (int64_t)(i + 1) * TB, Vt + pt * sp, Xs + pt * d, c + pt, nv,
-                              TB, SRC_KERNEL, 1));
+    const bool f64 = std::is_same<T, double>::value;
+    RowTile<T> t = make_tile<T>(base + jpanel_off(i), (int64_t)(i + 1) * TB,
+                                f64 ? reinterpret_cast<const T*>(Vt + pt * sp) : nullptr,
+                                f64 ? reinterpret_cast<const T*>(Xs + pt * d) : nullptr, c + pt, nv, TB, SRC_KERNEL, 1);
+    t.vt64 = Vt + pt * sp;
+    t.xs64 = Xs + pt * d;
+    rt.push_back(t);
   }
 }
 
@@ -424,8 +411,8 @@ void set_err(const Err& e) {
 // fit
 // ---------------------------------------------------------------------------
 template <typename TW>
-void build_window_run(lma_state& f, Run<TW>& run, TW* winbase, const TW* Xs, const TW* Vt, const TW* c,
-                      const TW* Ss) {
+void build_window_run(lma_state& f, Run<TW>& run, TW* winbase, const double* Xs, const double* Vt, const TW* c,
+                      const double* Ss) {
   const int Ts = (int)f.Ts;
   for (int64_t m = 0; m < f.M; ++m) {
     const WinGeom g = win_geom(f.bp, f.M, f.B, m);
@@ -436,8 +423,12 @@ void build_window_run(lma_state& f, Run<TW>& run, TW* winbase, const TW* Xs, con
     const int64_t ld = (int64_t)g.T * TB;
     for (int r = 0; r < Ts; ++r) {
       const int nv = (int)std::min<int64_t>(TB, f.s - (int64_t)r * TB);
-      run.rt.push_back(make_tile<TW>(rhs + (int64_t)r * TB * ld, ld, nullptr, Ss + (int64_t)r * TB * f.d, nullptr,
-                                     nv, TB, SRC_KERNEL, 0));
+      const bool f64 = std::is_same<TW, double>::value;
+      RowTile<TW> t = make_tile<TW>(rhs + (int64_t)r * TB * ld, ld, nullptr,
+                                    f64 ? reinterpret_cast<const TW*>(Ss + (int64_t)r * TB * f.d) : nullptr, nullptr,
+                                    nv, TB, SRC_KERNEL, 0);
+      t.xs64 = Ss + (int64_t)r * TB * f.d;
+      run.rt.push_back(t);
     }
     run.rt.push_back(make_tile<TW>(rhs + (int64_t)Ts * TB * ld, ld, nullptr, nullptr, nullptr, 1, TB, SRC_CVEC, 0));
   }
@@ -517,10 +508,7 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   f.o_Ss64 = ar.reserve(8 * s * d);
   f.o_c64 = ar.reserve(8 * n);
   if (mixed) {
-    f.o_Xs32 = ar.reserve(4 * n * d);
-    f.o_Ss32 = ar.reserve(4 * s * d);
     f.o_c32 = ar.reserve(4 * n);
-    f.o_Vt32 = ar.reserve(4 * n * sp);
   }
   f.o_Vt64 = ar.reserve(8 * n * sp);
   f.o_Lss = ar.reserve(8 * panel_elems(Ts, 0));
@@ -564,10 +552,6 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   f.o_xW = ar.reserve(8 * f.vec_elems);
   f.o_tJ = ar.reserve(8 * f.vec_elems);
   f.o_tW = ar.reserve(8 * f.vec_elems);
-  if (mixed) {
-    f.o_rJ = ar.reserve(8 * f.vec_elems);
-    f.o_rW = ar.reserve(8 * f.vec_elems);
-  }
   f.o_hJ = ar.reserve(8 * M * sp);
   f.o_hW = ar.reserve(8 * M * sp);
   f.o_cg = ar.reserve(8 * n);
@@ -593,8 +577,8 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     f.runS.schedule();
     // window run
     if (mixed) {
-      build_window_run<float>(f, f.runW32, f.ptr<float>(f.o_win), f.ptr<float>(f.o_Xs32), f.ptr<float>(f.o_Vt32),
-                              f.ptr<float>(f.o_c32), f.ptr<float>(f.o_Ss32));
+      build_window_run<float>(f, f.runW32, f.ptr<float>(f.o_win), f.ptr<double>(f.o_Xs64), f.ptr<double>(f.o_Vt64),
+                              f.ptr<float>(f.o_c32), f.ptr<double>(f.o_Ss64));
       f.runW32.schedule();
       build_summary<float>(f, f.sum32, f.ptr<float>(f.o_win));
     } else {
@@ -666,8 +650,8 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   double* logdiag = f.ptr<double>(f.o_logdiag);
   HIPCHK(hipMemsetAsync(status, 0, 4 * f.n_status, st));
   HIPCHK(hipMemsetAsync(logdiag, 0, 8 * f.n_logdiag, st));
-  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(p->X, n, (int)d, f.ie, f.ptr<double>(f.o_Xs64), f.ptr<float>(f.o_Xs32), st); });
-  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(p->S, s, (int)d, f.ie, f.ptr<double>(f.o_Ss64), f.ptr<float>(f.o_Ss32), st); });
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(p->X, n, (int)d, f.ie, f.ptr<double>(f.o_Xs64), nullptr, st); });
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(p->S, s, (int)d, f.ie, f.ptr<double>(f.o_Ss64), nullptr, st); });
   prof::timed(prof::OTHER, 0.0, st, [&] { launch_center(p->y, n, f.mu, f.ptr<double>(f.o_c64), f.ptr<float>(f.o_c32), st); });
   HIPCHK(hipGetLastError());
   const int maxTld = (int)(f.n_logdiag / (M + 2));
@@ -691,8 +675,9 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       a.j = j;
       a.items = run.d_items + run.upd_off[j];
       a.nitems = (int32_t)run.upd_n[j];
-      prof::timed(prof::UPDATE, prof::on ? run.update_flops(j, vlen > 0 ? s : 0) : 0.0, st,
-                  [&] { launch_update<TT>(a, st); });
+      double f64 = 0.0;
+      const double fl = prof::on ? run.update_flops(j, vlen > 0 ? s : 0, &f64) : 0.0;
+      prof::timed(prof::UPDATE, fl, st, [&] { launch_update<TT>(a, std::is_same<TT, float>::value, st); }, f64);
       HIPCHK(hipGetLastError());
       prof::timed(prof::DIAG, 0.0, st, [&] { launch_diag<TT>(a, run.d_plist + run.pl_off[j], (int)run.pl_n[j], st); });
       HIPCHK(hipGetLastError());
@@ -704,7 +689,6 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   };
   run_with_stride(f.runS, f.ptr<double>(f.o_Lss_inv), (int)M, 0);
   if (mixed) {
-    prof::timed(prof::OTHER, 0.0, st, [&] { launch_cast(f.ptr<double>(f.o_Vt64), f.ptr<float>(f.o_Vt32), n * sp, st); });
     run_with_stride(f.runW32, f.ptr<float>(f.o_win_inv), 0, (int)sp);
     prof::timed(prof::OTHER, 0.0, st, [&] { launch_tile_gemm<float>(reinterpret_cast<const GemmTerm<float>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
   } else {
@@ -839,29 +823,6 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       HIPCHK(hipGetLastError());
     };
     solve(f.ptr<double>(f.o_cg), nullptr, nullptr, 0);
-    if (mixed) {
-      // one step of iterative refinement against the float64 residual covariance
-      ResidArgs ra;
-      ra.w = f.wt;
-      ra.Xs = f.ptr<double>(f.o_Xs64);
-      ra.Vt = f.ptr<double>(f.o_Vt64);
-      ra.rhs_pt = f.ptr<double>(f.o_cg);
-      ra.xJ = f.ptr<double>(f.o_xJ);
-      ra.xW = f.ptr<double>(f.o_xW);
-      ra.hJ = f.ptr<double>(f.o_hJ);
-      ra.hW = f.ptr<double>(f.o_hW);
-      ra.rJ = f.ptr<double>(f.o_rJ);
-      ra.rW = f.ptr<double>(f.o_rW);
-      ra.d = (int)d;
-      ra.sp = (int)sp;
-      ra.sf2 = f.sf2;
-      ra.sn2 = f.sn2;
-      int maxTw = 0;
-      for (int64_t m = 0; m < M; ++m) maxTw = std::max(maxTw, (int)f.Tm[m]);
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_resid(ra, (int)M, maxTw, st); });
-      HIPCHK(hipGetLastError());
-      solve(nullptr, f.ptr<double>(f.o_rJ), f.ptr<double>(f.o_rW), 1);
-    }
   }
   // ---- read back status, log-diagonals, g, y_ddot, q
   std::vector<int32_t> hstat(f.n_status);
@@ -917,9 +878,9 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
 // predict
 // ---------------------------------------------------------------------------
 template <typename TW>
-void predict_windows(lma_state& f, Run<TW>& run, int64_t n_u, const std::vector<int64_t>& ubp, const TW* Us,
-                     const TW* VtU, TW* Xbuf, const std::vector<int64_t>& Xoff, TW* winbase, const TW* Xs,
-                     const TW* Vt, const TW* c) {
+void predict_windows(lma_state& f, Run<TW>& run, int64_t n_u, const std::vector<int64_t>& ubp, const double* Us,
+                     const double* VtU, TW* Xbuf, const std::vector<int64_t>& Xoff, TW* winbase, const double* Xs,
+                     const double* Vt, const TW* c) {
   for (int64_t m = 0; m < f.M; ++m) {
     const WinGeom g = win_geom(f.bp, f.M, f.B, m);
     const int64_t qhi = std::min(m + f.B, f.M - 1);
@@ -935,8 +896,14 @@ void predict_windows(lma_state& f, Run<TW>& run, int64_t n_u, const std::vector<
     for (int r = 0; r < R; ++r) {
       const int nv = (int)std::min<int64_t>(TB, nr - (int64_t)r * TB);
       const int64_t pt = r0 + (int64_t)r * TB;
-      run.rt.push_back(make_tile<TW>(Xbuf + Xoff[m] + (int64_t)r * TB * ld, ld, VtU + pt * f.sp, Us + pt * f.d,
-                                     nullptr, nv, nv, SRC_KERNEL, 0));
+      const bool f64 = std::is_same<TW, double>::value;
+      RowTile<TW> t = make_tile<TW>(Xbuf + Xoff[m] + (int64_t)r * TB * ld, ld,
+                                    f64 ? reinterpret_cast<const TW*>(VtU + pt * f.sp) : nullptr,
+                                    f64 ? reinterpret_cast<const TW*>(Us + pt * f.d) : nullptr, nullptr, nv, nv,
+                                    SRC_KERNEL, 0);
+      t.vt64 = VtU + pt * f.sp;
+      t.xs64 = Us + pt * f.d;
+      run.rt.push_back(t);
     }
   }
   (void)n_u;
@@ -970,9 +937,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   const int64_t ldG = sp + TB;
   Arena ar;
   const int64_t o_Us64 = ar.reserve(8 * n_u * d);
-  const int64_t o_Us32 = mixed ? ar.reserve(4 * n_u * d) : -1;
   const int64_t o_VtU64 = ar.reserve(8 * n_u * sp);
-  const int64_t o_VtU32 = mixed ? ar.reserve(4 * n_u * sp) : -1;
   const int64_t o_X = ar.reserve((int64_t)sizeof(TW) * xel);
   const int64_t o_G = ar.reserve(8 * n_u * ldG);
   const int64_t o_vn = ar.reserve(8 * n_u);
@@ -1009,10 +974,10 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     }
     runS.schedule();
     // window runs in solve-only mode
-    const TW* Us = mixed ? (const TW*)at<float>(ar, o_Us32) : (const TW*)at<double>(ar, o_Us64);
-    const TW* VtU = mixed ? (const TW*)at<float>(ar, o_VtU32) : (const TW*)at<double>(ar, o_VtU64);
-    const TW* Xs = mixed ? (const TW*)f.ptr<float>(f.o_Xs32) : (const TW*)f.ptr<double>(f.o_Xs64);
-    const TW* Vt = mixed ? (const TW*)f.ptr<float>(f.o_Vt32) : (const TW*)f.ptr<double>(f.o_Vt64);
+    const double* Us = at<double>(ar, o_Us64);
+    const double* VtU = at<double>(ar, o_VtU64);
+    const double* Xs = f.ptr<double>(f.o_Xs64);
+    const double* Vt = f.ptr<double>(f.o_Vt64);
     const TW* c = mixed ? (const TW*)f.ptr<float>(f.o_c32) : (const TW*)f.ptr<double>(f.o_c64);
     TW* winbase = reinterpret_cast<TW*>(f.ptr<char>(f.o_win));
     if (!var) return;
@@ -1146,7 +1111,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   double* ldg = at<double>(ar, o_ld);
   HIPCHK(hipMemsetAsync(stat, 0, 4 * (M + 2), st));
   // scale test inputs
-  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(U, n_u, (int)d, f.ie, at<double>(ar, o_Us64), mixed ? at<float>(ar, o_Us32) : nullptr, st); });
+  prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(U, n_u, (int)d, f.ie, at<double>(ar, o_Us64), nullptr, st); });
   HIPCHK(hipGetLastError());
   auto exec = [&](auto& run, auto* invdiag, int vlen) {
     using TT = typename std::remove_pointer<decltype(invdiag)>::type;
@@ -1166,8 +1131,9 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
       a.j = j;
       a.items = run.d_items + run.upd_off[j];
       a.nitems = (int32_t)run.upd_n[j];
-      prof::timed(prof::UPDATE, prof::on ? run.update_flops(j, vlen > 0 ? f.s : 0) : 0.0, st,
-                  [&] { launch_update<TT>(a, st); });
+      double f64 = 0.0;
+      const double fl = prof::on ? run.update_flops(j, vlen > 0 ? f.s : 0, &f64) : 0.0;
+      prof::timed(prof::UPDATE, fl, st, [&] { launch_update<TT>(a, std::is_same<TT, float>::value, st); }, f64);
       HIPCHK(hipGetLastError());
       a.items = run.d_items + run.trs_off[j];
       a.nitems = (int32_t)run.trs_n[j];
@@ -1205,7 +1171,6 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     prof::flush();
     return;
   }
-  if (mixed) launch_cast(at<double>(ar, o_VtU64), at<float>(ar, o_VtU32), n_u * sp, st);
   exec(runW, reinterpret_cast<TW*>(f.ptr<char>(f.o_win_inv)), (int)sp);
   for (int dl = 0; dl <= f.B; ++dl) {
     const int a0 = dl_split[dl], a1 = dl_split[dl + 1];

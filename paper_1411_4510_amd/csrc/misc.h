@@ -110,23 +110,6 @@ struct VecSolveArgs {
   int accumulate;
 };
 
-// Residual of the vector solves in float64: r = rhs - R_X x, with
-// R_X x = K_XX x + sigma_n^2 x - V_X^T (V_X x) and h = V_X x precomputed.
-struct ResidArgs {
-  WinTab w;
-  const double* Xs;        // scaled training inputs [n][d]
-  const double* Vt;        // [n][sp]
-  const double* rhs_pt;    // per point right-hand side
-  const double* xJ;
-  const double* xW;
-  const double* hJ;        // [M][sp]
-  const double* hW;
-  double* rJ;
-  double* rW;
-  int d, sp;
-  double sf2, sn2;
-};
-
 // h = V_X x for X = J_m (hJ) and X = W_m (hW).
 struct HArgs {
   WinTab w;
@@ -172,7 +155,6 @@ struct MeanArgs {
 
 template <typename TW>
 void launch_vec_solve(const VecSolveArgs<TW>& a, int M, hipStream_t st);
-void launch_resid(const ResidArgs& a, int M, int maxT, hipStream_t st);
 void launch_h(const HArgs& a, hipStream_t st);
 void launch_cg(const CgArgs& a, hipStream_t st);
 void launch_mean(const MeanArgs& a, hipStream_t st);

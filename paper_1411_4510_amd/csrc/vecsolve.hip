@@ -7,9 +7,7 @@
 // (Woodbury on Sigma_bar_DD = Q + R_bar and the signed window sum of
 // R_bar_DD^-1 that the banded factor of Lemma 1 gives; the separator term of
 // window q cancels against its own leading block.)  Only vector solves are
-// needed, so they run in float64 arithmetic even on float32 factors, and in
-// mixed precision one step of iterative refinement against the float64
-// residual covariance brings beta to float64 accuracy.
+// needed, so they run in float64 arithmetic even on float32 factors.
 #include "engine.h"
 #include "misc.h"
 
@@ -144,53 +142,6 @@ __global__ __launch_bounds__(128) void k_h(HArgs a) {
   a.hW[(int64_t)m * a.sp + k] = hw;
 }
 
-// r = rhs - R_X x for row tile i of window m (X = J_m, and X = W_m if i < tw).
-__global__ __launch_bounds__(256) void k_resid(ResidArgs a) {
-  __shared__ double part[4][TB];
-  const int m = blockIdx.x, i = blockIdx.y, tid = threadIdx.x;
-  const WinTab& w = a.w;
-  const int T = w.T[m], tw = w.tw[m];
-  if (i >= T) return;
-  const int64_t vo = w.vec[m];
-  const int r = tid & (TB - 1), h = tid >> 7;
-  const int row = i * TB + r;
-  bool va;
-  const int64_t pa = win_point(w, m, row, va);
-  const double* xa = a.Xs + (va ? pa : 0) * a.d;
-  double sj = 0.0, sw = 0.0;
-  if (va) {
-    for (int c = h; c < T * TB; c += 2) {
-      bool vb;
-      const int64_t pb = win_point(w, m, c, vb);
-      if (!vb) continue;
-      const double kv = a.sf2 * exp(-0.5 * sqd(xa, a.Xs + pb * a.d, a.d));
-      sj += kv * a.xJ[vo + c];
-      if (c < tw * TB && i < tw) sw += kv * a.xW[vo + c];
-    }
-  }
-  part[h][r] = sj;
-  part[2 + h][r] = sw;
-  __syncthreads();
-  if (tid < TB) {
-    double resJ = 0.0, resW = 0.0;
-    if (va) {
-      const double* vt = a.Vt + pa * a.sp;
-      const double* hj = a.hJ + (int64_t)m * a.sp;
-      const double* hw = a.hW + (int64_t)m * a.sp;
-      double qj = 0.0, qw = 0.0;
-      for (int k = 0; k < a.sp; ++k) {
-        qj += vt[k] * hj[k];
-        qw += vt[k] * hw[k];
-      }
-      const double rhs = a.rhs_pt[pa];
-      resJ = rhs - (part[0][r] + part[1][r] + a.sn2 * a.xJ[vo + row] - qj);
-      if (i < tw) resW = rhs - (part[2][r] + part[3][r] + a.sn2 * a.xW[vo + row] - qw);
-    }
-    a.rJ[vo + row] = resJ;
-    if (i < tw) a.rW[vo + row] = resW;
-  }
-}
-
 // c' = c - K_DS g, one wave per training point.
 __global__ __launch_bounds__(256) void k_cg(CgArgs a) {
   const int lane = threadIdx.x & 63;
@@ -245,9 +196,6 @@ __global__ __launch_bounds__(256) void k_mean(MeanArgs a) {
 template <typename TW>
 void launch_vec_solve(const VecSolveArgs<TW>& a, int M, hipStream_t st) {
   hipLaunchKernelGGL(k_vec_solve<TW>, dim3(M), dim3(256), 0, st, a);
-}
-void launch_resid(const ResidArgs& a, int M, int maxT, hipStream_t st) {
-  hipLaunchKernelGGL(k_resid, dim3(M, maxT), dim3(256), 0, st, a);
 }
 void launch_h(const HArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_h, dim3(a.M, a.sp / TB), dim3(TB), 0, st, a);
