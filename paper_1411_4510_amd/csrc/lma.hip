@@ -73,6 +73,7 @@ void ensure_init() {
   if (g_inited) return;
   HIPCHK(engine_init());
   HIPCHK(misc_init());
+  HIPCHK(vecsolve_init());
   g_inited = true;
 }
 
@@ -273,7 +274,7 @@ struct lma_state {
   int64_t n_logdiag = 0, n_status = 0;
   // mean path: window table, beta vectors and their V-projections
   int64_t o_wt = -1, o_xJ = -1, o_xW = -1, o_tJ = -1, o_tW = -1, o_hJ = -1, o_hW = -1,
-          o_cg = -1, vec_elems = 0;
+          o_cg = -1, o_dg = -1, o_tvec = -1, o_rho = -1, vec_elems = 0;
   WinTab wt;
   // window geometry
   std::vector<int32_t> Tm, twm;
@@ -547,14 +548,19 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   f.o_status = ar.reserve(4 * f.n_status);
   f.vec_elems = 0;
   for (int64_t m = 0; m < M; ++m) f.vec_elems += (int64_t)f.Tm[m] * TB;
-  f.o_wt = ar.reserve(8 * 9 * M);
+  f.o_wt = ar.reserve(8 * 10 * M);
   f.o_xJ = ar.reserve(8 * f.vec_elems);
   f.o_xW = ar.reserve(8 * f.vec_elems);
   f.o_tJ = ar.reserve(8 * f.vec_elems);
   f.o_tW = ar.reserve(8 * f.vec_elems);
   f.o_hJ = ar.reserve(8 * M * sp);
   f.o_hW = ar.reserve(8 * M * sp);
-  f.o_cg = ar.reserve(8 * n);
+  if (mixed) {
+    f.o_cg = ar.reserve(8 * n);
+    f.o_dg = ar.reserve(8 * sp);
+    f.o_tvec = ar.reserve(8 * sp);
+    f.o_rho = ar.reserve(8 * sp);
+  }
 
   // engine runs (built with arena offsets; pointers fixed after allocation)
   // Reserve space for run metadata: build runs against a null base first to size them.
@@ -729,7 +735,7 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   }
   // ---- beta_X = R_X^-1 (c_X - K_XS g) for every window and separator
   {
-    std::vector<int64_t> tab(9 * M);
+    std::vector<int64_t> tab(10 * M);
     int64_t* t_wstart = tab.data();
     int64_t* t_wlen = t_wstart + M;
     int64_t* t_dstart = t_wlen + M;
@@ -737,9 +743,11 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     int64_t* t_panel = t_dlen + M;
     int64_t* t_inv = t_panel + M;
     int64_t* t_vec = t_inv + M;
-    int32_t* t_T = reinterpret_cast<int32_t*>(t_vec + M);
+    int64_t* t_rhs = t_vec + M;
+    int32_t* t_T = reinterpret_cast<int32_t*>(t_rhs + M);
     int32_t* t_tw = t_T + M;
     int64_t inv_acc = 0, vec_acc = 0;
+    int maxTw = 0;
     for (int64_t m = 0; m < M; ++m) {
       const WinGeom g = win_geom(f.bp, M, f.B, m);
       t_wstart[m] = g.wstart;
@@ -749,14 +757,16 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       t_panel[m] = f.win_off[m];
       t_inv[m] = inv_acc;
       t_vec[m] = vec_acc;
+      t_rhs[m] = f.win_off[m] + jpanel_off(g.T);
       t_T[m] = g.T;
       t_tw[m] = g.tw;
       inv_acc += (int64_t)g.T * TB * TB;
       vec_acc += (int64_t)g.T * TB;
+      maxTw = std::max(maxTw, g.T);
     }
     f.wt_host = tab;
     char* dt = f.ptr<char>(f.o_wt);
-    HIPCHK(hipMemcpyAsync(dt, f.wt_host.data(), 8 * 9 * M, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(dt, f.wt_host.data(), 8 * 10 * M, hipMemcpyHostToDevice, st));
     const int64_t* dtab = reinterpret_cast<const int64_t*>(dt);
     f.wt.wstart = dtab;
     f.wt.wlen = dtab + M;
@@ -765,64 +775,123 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     f.wt.panel = dtab + 4 * M;
     f.wt.inv = dtab + 5 * M;
     f.wt.vec = dtab + 6 * M;
-    f.wt.T = reinterpret_cast<const int32_t*>(dtab + 7 * M);
+    f.wt.rhs = dtab + 7 * M;
+    f.wt.T = reinterpret_cast<const int32_t*>(dtab + 8 * M);
     f.wt.tw = f.wt.T + M;
-    CgArgs ca;
-    ca.n = n;
-    ca.d = (int)d;
-    ca.s = (int)s;
-    ca.Xs = f.ptr<double>(f.o_Xs64);
-    ca.Ss = f.ptr<double>(f.o_Ss64);
-    ca.c = f.ptr<double>(f.o_c64);
-    ca.g = f.ptr<double>(f.o_g);
-    ca.sf2 = f.sf2;
-    ca.out = f.ptr<double>(f.o_cg);
-    prof::timed(prof::OTHER, 0.0, st, [&] { launch_cg(ca, st); });
-    HIPCHK(hipGetLastError());
+    double* xJ = f.ptr<double>(f.o_xJ);
+    double* xW = f.ptr<double>(f.o_xW);
+    double* tJ = f.ptr<double>(f.o_tJ);
+    double* tW = f.ptr<double>(f.o_tW);
+    double* g = f.ptr<double>(f.o_g);
     HArgs ha;
     ha.w = f.wt;
     ha.Vt = f.ptr<double>(f.o_Vt64);
-    ha.xJ = f.ptr<double>(f.o_xJ);
-    ha.xW = f.ptr<double>(f.o_xW);
+    ha.xJ = xJ;
+    ha.xW = xW;
     ha.hJ = f.ptr<double>(f.o_hJ);
     ha.hW = f.ptr<double>(f.o_hW);
     ha.sp = (int)sp;
     ha.M = (int)M;
-    auto solve = [&](const double* rhs_pt, const double* rJ, const double* rW, int accumulate) {
-      if (mixed) {
-        VecSolveArgs<float> va;
-        va.w = f.wt;
-        va.panels = f.ptr<float>(f.o_win);
-        va.invs = f.ptr<float>(f.o_win_inv);
-        va.rhs_pt = rhs_pt;
-        va.rhsJ = rJ;
-        va.rhsW = rW;
-        va.tJ = f.ptr<double>(f.o_tJ);
-        va.tW = f.ptr<double>(f.o_tW);
-        va.xJ = f.ptr<double>(f.o_xJ);
-        va.xW = f.ptr<double>(f.o_xW);
-        va.accumulate = accumulate;
-        prof::timed(prof::OTHER, 0.0, st, [&] { launch_vec_solve<float>(va, (int)M, st); });
-      } else {
-        VecSolveArgs<double> va;
-        va.w = f.wt;
-        va.panels = f.ptr<double>(f.o_win);
-        va.invs = f.ptr<double>(f.o_win_inv);
-        va.rhs_pt = rhs_pt;
-        va.rhsJ = rJ;
-        va.rhsW = rW;
-        va.tJ = f.ptr<double>(f.o_tJ);
-        va.tW = f.ptr<double>(f.o_tW);
-        va.xJ = f.ptr<double>(f.o_xJ);
-        va.xW = f.ptr<double>(f.o_xW);
-        va.accumulate = accumulate;
-        prof::timed(prof::OTHER, 0.0, st, [&] { launch_vec_solve<double>(va, (int)M, st); });
-      }
-      HIPCHK(hipGetLastError());
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+    auto winvec = [&](auto* panels, auto* invs, double* vJ, double* vW) {
+      using TT = typename std::remove_const<typename std::remove_pointer<decltype(panels)>::type>::type;
+      WinVecArgs<TT> va;
+      va.w = f.wt;
+      va.panels = panels;
+      va.invs = invs;
+      va.sp = (int)sp;
+      va.s = (int)s;
+      va.g = g;
+      va.vJ = vJ;
+      va.vW = vW;
+      return va;
+    };
+    // beta from the whitened right-hand sides (forward half) and a backward solve
+    auto beta_solve = [&](auto* panels, auto* invs) {
+      auto va = winvec(panels, invs, xJ, xW);
+      using TT = typename std::remove_const<typename std::remove_pointer<decltype(panels)>::type>::type;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_ycp<TT>(va, (int)M, maxTw, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_bwd<TT>(va, (int)M, st); });
       HIPCHK(hipGetLastError());
     };
-    solve(f.ptr<double>(f.o_cg), nullptr, nullptr, 0);
+    auto full_solve = [&](auto* panels, auto* invs, double* vJ, double* vW) {
+      auto va = winvec(panels, invs, vJ, vW);
+      using TT = typename std::remove_const<typename std::remove_pointer<decltype(panels)>::type>::type;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_fwd<TT>(va, (int)M, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_bwd<TT>(va, (int)M, st); });
+      HIPCHK(hipGetLastError());
+    };
+    if (!mixed) {
+      beta_solve(f.ptr<double>(f.o_win), f.ptr<double>(f.o_win_inv));
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+      HIPCHK(hipGetLastError());
+    } else {
+      const float* P = f.ptr<float>(f.o_win);
+      const float* I = f.ptr<float>(f.o_win_inv);
+      double* cg = f.ptr<double>(f.o_cg);
+      double* dg = f.ptr<double>(f.o_dg);
+      double* tvec = f.ptr<double>(f.o_tvec);
+      // 1. beta0 with the float32 factors
+      beta_solve(P, I);
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+      // 2. one refinement of beta against the float64 residual covariance
+      CgArgs ca;
+      ca.n = n;
+      ca.d = (int)d;
+      ca.s = (int)s;
+      ca.Xs = f.ptr<double>(f.o_Xs64);
+      ca.Ss = f.ptr<double>(f.o_Ss64);
+      ca.c = f.ptr<double>(f.o_c64);
+      ca.g = g;
+      ca.sf2 = f.sf2;
+      ca.out = cg;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_cg(ca, st); });
+      KmvArgs ka;
+      ka.w = f.wt;
+      ka.Xs = f.ptr<double>(f.o_Xs64);
+      ka.Vt = f.ptr<double>(f.o_Vt64);
+      ka.rhs_pt = cg;
+      ka.xJ = xJ;
+      ka.xW = xW;
+      ka.hJ = ha.hJ;
+      ka.hW = ha.hW;
+      ka.rJ = tJ;
+      ka.rW = tW;
+      ka.d = (int)d;
+      ka.sp = (int)sp;
+      ka.sf2 = f.sf2;
+      ka.sn2 = f.sn2;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_kmv(ka, (int)M, maxTw, st); });
+      full_solve(P, I, tJ, tW);
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_axpy2(xJ, xW, tJ, tW, 1.0, f.vec_elems, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+      // 3. global correction: rho = y_ddot - Sigma_ddot g with exact window solves
+      GresArgs gr;
+      gr.L = f.ptr<double>(f.o_Lss);
+      gr.hJ = ha.hJ;
+      gr.hW = ha.hW;
+      gr.g = g;
+      gr.rho = f.ptr<double>(f.o_rho);
+      gr.M = (int)M;
+      gr.sp = (int)sp;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_gres(gr, st); });
+      SolveArgs so;
+      so.L = f.ptr<double>(f.o_Ldd);
+      so.inv = f.ptr<double>(f.o_Ldd_inv);
+      so.A = f.ptr<double>(f.o_Sdd);
+      so.b = gr.rho;
+      so.g = dg;
+      so.sp = (int)sp;
+      so.iters = 1;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_global_solve(so, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_gupdate(gr.L, dg, g, tvec, (int)sp, st); });
+      // 4. beta -= R_X^-1 K_XS dg  (K_XS dg = V_X^T L_SS^T dg); float32 factors suffice for the correction
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_vdot(f.ptr<double>(f.o_Vt64), tvec, cg, n, (int)sp, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_gather(f.wt, cg, tJ, tW, (int)M, maxTw, st); });
+      full_solve(P, I, tJ, tW);
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_axpy2(xJ, xW, tJ, tW, -1.0, f.vec_elems, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+      HIPCHK(hipGetLastError());
+    }
   }
   // ---- read back status, log-diagonals, g, y_ddot, q
   std::vector<int32_t> hstat(f.n_status);

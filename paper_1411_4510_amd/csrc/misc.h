@@ -73,6 +73,7 @@ void launch_pred_var(const PredArgs& a, hipStream_t st);
 template <typename T>
 void launch_pred_xi(const XiArgs<T>& a, hipStream_t st);
 hipError_t misc_init();
+hipError_t vecsolve_init();
 hipError_t engine_init();
 
 }  // namespace lma
@@ -90,24 +91,48 @@ struct WinTab {
   const int64_t* panel;    // element offset of window m's factor panels
   const int64_t* inv;      // element offset of window m's inverted diagonal tiles
   const int64_t* vec;      // offset of window m's vectors (T*128 doubles)
+  const int64_t* rhs;      // element offset of window m's right-hand-side rows (support rows, then the output row)
 };
 
-// Vector solves with the stored window factors:
-//   xJ = R_{J_m}^-1 rhsJ,  xW = R_{W_m}^-1 rhsW   (R_W = L11 L11^T, the leading block)
-// rhs is gathered from a per-point array (c - K_DS g) or taken per window.
+// Vector work on the stored window factors (window layout: T*128 doubles per
+// window, W_m rows first).  vJ holds vectors of length |J_m|, vW of |W_m|.
 template <typename TW>
-struct VecSolveArgs {
+struct WinVecArgs {
   WinTab w;
-  const TW* panels;
-  const TW* invs;
-  const double* rhs_pt;    // per training point, or null
-  const double* rhsJ;      // per window layout when rhs_pt is null
-  const double* rhsW;
-  double* tJ;              // scratch, window layout
-  double* tW;
-  double* xJ;              // outputs, window layout
-  double* xW;
-  int accumulate;
+  const TW* panels;        // window factor storage
+  const TW* invs;          // inverted diagonal tiles
+  int sp, s;
+  const double* g;         // [sp] (k_ycp)
+  double* vJ;
+  double* vW;
+};
+
+// r = c' - R_X x in float64 (R_X x = K_XX x + sigma_n^2 x - V_X^T h, h = V_X x),
+// for X = J_m and X = W_m.
+struct KmvArgs {
+  WinTab w;
+  const double* Xs;        // scaled training inputs [n][d]
+  const double* Vt;        // [n][sp]
+  const double* rhs_pt;    // c' per training point
+  const double* xJ;
+  const double* xW;
+  const double* hJ;        // [M][sp]
+  const double* hW;
+  double* rJ;
+  double* rW;
+  int d, sp;
+  double sf2, sn2;
+};
+
+// Global correction of g (mixed precision): H = sum_m (hJ_m - hW_m),
+// rho = L_SS (H - L_SS^T g)  (= y_ddot - Sigma_ddot g with exact window solves).
+struct GresArgs {
+  const double* L;         // tiled Cholesky factor of Sigma_SS
+  const double* hJ;
+  const double* hW;
+  const double* g;
+  double* rho;             // [sp]
+  int M, sp;
 };
 
 // h = V_X x for X = J_m (hJ) and X = W_m (hW).
@@ -154,7 +179,22 @@ struct MeanArgs {
 };
 
 template <typename TW>
-void launch_vec_solve(const VecSolveArgs<TW>& a, int M, hipStream_t st);
+void launch_ycp(const WinVecArgs<TW>& a, int M, int maxT, hipStream_t st);
+template <typename TW>
+void launch_fwd(const WinVecArgs<TW>& a, int M, hipStream_t st);
+template <typename TW>
+void launch_bwd(const WinVecArgs<TW>& a, int M, hipStream_t st);
+void launch_kmv(const KmvArgs& a, int M, int maxT, hipStream_t st);
+void launch_gres(const GresArgs& a, hipStream_t st);
+// g += dg and t = L_SS^T dg (one workgroup)
+void launch_gupdate(const double* L, const double* dg, double* g, double* t, int sp, hipStream_t st);
+// out[i] = Vt[i] . t for every training point (one wave per point)
+void launch_vdot(const double* Vt, const double* t, double* out, int64_t n, int sp, hipStream_t st);
+// gather a per-point vector into window layout (vJ and vW)
+void launch_gather(const WinTab& w, const double* pt, double* vJ, double* vW, int M, int maxT, hipStream_t st);
+// vJ += alpha * xJ, vW += alpha * xW over the window layout of length nvec
+void launch_axpy2(double* vJ, double* vW, const double* xJ, const double* xW, double alpha, int64_t nvec,
+                  hipStream_t st);
 void launch_h(const HArgs& a, hipStream_t st);
 void launch_cg(const CgArgs& a, hipStream_t st);
 void launch_mean(const MeanArgs& a, hipStream_t st);
