@@ -59,9 +59,14 @@ __device__ inline int xcd_logical(int bid, int nb) {
 }
 
 // acc[ra][rb] += A[arow0 + 16 ra + i, k] * Bm[brow0 + 16 rb + j, k] over k in [k0, k1).
+// Rows at or past anr / bnr are read from row 0 instead (always a valid
+// address): they only feed output rows / columns that the callers either do
+// not store or overwrite with their exact value (padding).  Loads are
+// unconditional and rotate through PF+1 register slots, so the chunk in use
+// never waits for the chunks in flight.
 // PERMA feeds the A rows of each 16-row sub-tile in the order r(4a+b) = a+4b, which
 // turns the float32 16x16 output layout into the float64 one (row l/16 + 4v).
-template <typename Tin, typename Tc, bool PERMA = false>
+template <typename Tin, typename Tc, bool PERMA = false, int PF = 2>
 __device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
                                           const Tin* __restrict__ A, int64_t lda, int anr,
                                           const Tin* __restrict__ Bm, int64_t ldb, int bnr,
@@ -70,53 +75,59 @@ __device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
   const int r16 = lane & 15, kq = (lane >> 4) << 2;
   const Tin* pa[4];
   const Tin* pb[4];
-  bool va[4], vb[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int ra = arow0 + t * 16 + (PERMA ? ((r16 >> 2) | ((r16 & 3) << 2)) : r16);
-    va[t] = ra < anr;
-    pa[t] = A + (int64_t)(va[t] ? ra : 0) * lda + k0 + kq;
+    pa[t] = A + (int64_t)(ra < anr ? ra : 0) * lda + k0 + kq;
     const int rb = brow0 + t * 16 + r16;
-    vb[t] = rb < bnr;
-    pb[t] = Bm + (int64_t)(vb[t] ? rb : 0) * ldb + k0 + kq;
+    pb[t] = Bm + (int64_t)(rb < bnr ? rb : 0) * ldb + k0 + kq;
   }
   const int nc = (k1 - k0) >> 4;
   if (nc <= 0) return;
-  vin ca[4], cb[4], na[4], nb[4];
-  const vin zero = {Tin(0), Tin(0), Tin(0), Tin(0)};
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    ca[t] = va[t] ? *(const vin*)(pa[t]) : zero;
-    cb[t] = vb[t] ? *(const vin*)(pb[t]) : zero;
+  vin sa[PF + 1][4], sb[PF + 1][4];
+  // chunk x lives in slot x % (PF+1)
+#define LMA_LOAD_CHUNK(X, SLOT)                                \
+  {                                                            \
+    const int off_ = (X) << 4;                                 \
+    const int slot_ = (SLOT);                                  \
+    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {         \
+      sa[slot_][u_] = *(const vin*)(pa[u_] + off_);            \
+      sb[slot_][u_] = *(const vin*)(pb[u_] + off_);            \
+    }                                                          \
   }
-  for (int c = 0; c < nc; ++c) {
-    const bool more = c + 1 < nc;
-    if (more) {
-      const int off = (c + 1) << 4;
+#define LMA_MMA_SLOT(SLOT)                                                                 \
+  {                                                                                        \
+    const int slot_ = (SLOT);                                                              \
+    _Pragma("unroll") for (int e = 0; e < 4; ++e) {                                        \
+      _Pragma("unroll") for (int ra = 0; ra < 4; ++ra) {                                   \
+        _Pragma("unroll") for (int rb = 0; rb < 4; ++rb) {                                 \
+          acc[ra][rb] = Mfma<Tc>::op((Tc)sa[slot_][ra][e], (Tc)sb[slot_][rb][e], acc[ra][rb]); \
+        }                                                                                  \
+      }                                                                                    \
+    }                                                                                      \
+  }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        na[t] = va[t] ? *(const vin*)(pa[t] + off) : zero;
-        nb[t] = vb[t] ? *(const vin*)(pb[t] + off) : zero;
-      }
-    }
+  for (int p = 0; p < PF; ++p)
+    if (p < nc) LMA_LOAD_CHUNK(p, p)
+  int c = 0;
+  // steady state: every prefetch is in range, no branches in the body
+  for (; c + 2 * PF < nc; c += PF + 1) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-#pragma unroll
-      for (int ra = 0; ra < 4; ++ra) {
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-          acc[ra][rb] = Mfma<Tc>::op((Tc)ca[ra][e], (Tc)cb[rb][e], acc[ra][rb]);
-        }
-      }
-    }
-    if (more) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        ca[t] = na[t];
-        cb[t] = nb[t];
-      }
+    for (int q = 0; q <= PF; ++q) {
+      LMA_LOAD_CHUNK(c + q + PF, (q + PF) % (PF + 1))
+      LMA_MMA_SLOT(q)
     }
   }
+  // tail: at most 2*PF+1 chunks, slots known at compile time
+#pragma unroll
+  for (int t = 0; t <= 2 * PF; ++t) {
+    if (c + t < nc) {
+      if (c + t + PF < nc) LMA_LOAD_CHUNK(c + t + PF, (t + PF) % (PF + 1))
+      LMA_MMA_SLOT(t % (PF + 1))
+    }
+  }
+#undef LMA_LOAD_CHUNK
+#undef LMA_MMA_SLOT
 }
 
 template <typename Tc>
@@ -204,7 +215,9 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
           kv = TK(1);
         }
         T val;
-        if constexpr (MIXED)
+        if (row >= ri.nvalid || col >= rj.nvalid)
+          val = (T)kv;  // padding: identity on the diagonal tile, zero elsewhere
+        else if constexpr (MIXED)
           val = (T)(kv - accv[rs][cs][v]) - accl[rs][cs][v];
         else
           val = (T)(kv - accv[rs][cs][v]);
