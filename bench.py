@@ -65,6 +65,24 @@ def algorithmic_flops(p):
     return float(f_fit), float(f_pred)
 
 
+def measured_traffic(kernel_mode):
+    """HBM bytes per k_update launch from the committed PMC runs, if the kernel
+    source has not changed since they were taken (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_update_fp64_n524288_traffic.json")
+    if kernel_mode != "fp64" or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for fn in ("engine.hip", "engine.h"):
+        with open(os.path.join(ROOT, "paper_1411_4510_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(p, budget_s=25.0):
     """The oracle timed on a bounded sample: support part (L_SS, V over all of
     D and U) plus a spread of windows, scaled to all M windows by their cubic
@@ -114,6 +132,8 @@ def main():
     ap.add_argument("--no-lml", action="store_true", help="skip the separate LML-rate measurement")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--small", action="store_true", help="n=65536 workload (quick check)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB mebibytes (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -127,6 +147,15 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
+        return
     lma.load()
     t0 = time.perf_counter()
     p = synth.make_config(1) if args.small else synth.make_config(2)
@@ -186,7 +215,8 @@ def main():
     peak = prof["update_alg_flops"] / t_ideal if t_ideal > 0 else PEAK[head]
     roofline = {"bound": "mfma", "kernel": f"k_update<{'double' if head == 'fp64' else 'float, mixed'}>",
                 "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": measured_traffic(head) if not args.small else None,
+                "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                 "avg_launch_ms": prof["update_ms"] / max(prof["update_launches"], 1),
                 "launches": prof["update_launches"],
                 "path_alg_tflops": (f_fit + f_pred) / res[head]["s_per_step"] / 1e12,
