@@ -23,7 +23,7 @@ LMA_OK, LMA_E_ARG, LMA_E_NOT_PD, LMA_E_HIP, LMA_E_NOMEM = 0, 1, 2, 3, 4
 PRECISION = {"fp64": 0, "mixed": 1}
 EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml",
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
-           "lma_profile_read")
+           "lma_profile_read", "lma_release_cache")
 
 
 class LmaError(RuntimeError):
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
     lib.lma_last_error.restype = ctypes.c_char_p
     lib.lma_failed_block.restype = i64
     lib.lma_version.restype = ctypes.c_char_p
+    lib.lma_release_cache.argtypes = []
+    lib.lma_release_cache.restype = None
     lib.lma_profile_enable.argtypes = [ctypes.c_int]
     lib.lma_profile_enable.restype = None
     lib.lma_profile_read.argtypes = [ctypes.POINTER(Profile), ctypes.c_int]
@@ -217,6 +219,12 @@ def profile_read(reset=True):
     out = Profile()
     _check(_lib.lma_profile_read(ctypes.byref(out), 1 if reset else 0))
     return out.as_dict()
+
+
+def release_cache():
+    """Free the device memory the library keeps for reuse between calls."""
+    load()
+    _lib.lma_release_cache()
 
 
 def version():

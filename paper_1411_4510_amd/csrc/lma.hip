@@ -22,6 +22,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <string>
 #include <vector>
@@ -67,6 +68,72 @@ template <typename T>
 T* at(const Arena& ar, int64_t off) {
   return reinterpret_cast<T*>(ar.base + off);
 }
+
+// Device blocks released by lma_free / lma_predict are kept (at most two) and
+// reused by the next call that fits in them: a state at the n=524288
+// workload is ~95 GB and mapping it anew each fit costs a few hundred
+// milliseconds.  lma_release_cache() returns them to the runtime.
+namespace devcache {
+struct Block {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int device = -1;
+};
+std::mutex mu;
+Block slots[2];
+void free_all_locked() {
+  for (Block& b : slots) {
+    if (b.p) (void)hipFree(b.p);
+    b = Block{};
+  }
+}
+void* get(size_t bytes) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  int best = -1;
+  for (int i = 0; i < 2; ++i)
+    if (slots[i].p && slots[i].device == dev && slots[i].bytes >= bytes && slots[i].bytes <= 2 * bytes + (64 << 20) &&
+        (best < 0 || slots[i].bytes < slots[best].bytes))
+      best = i;
+  if (best >= 0) {
+    void* p = slots[best].p;
+    slots[best] = Block{};
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    free_all_locked();  // make room, then try once more
+    p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+  }
+  return p;
+}
+void put(void* p, size_t bytes) {
+  if (!p) return;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(mu);
+  int victim = 0;
+  for (int i = 0; i < 2; ++i)
+    if (!slots[i].p) {
+      victim = i;
+      break;
+    } else if (slots[i].bytes < slots[victim].bytes) {
+      victim = i;
+    }
+  if (slots[victim].p) (void)hipFree(slots[victim].p);
+  slots[victim] = Block{p, bytes, dev};
+}
+void release() {
+  std::lock_guard<std::mutex> lk(mu);
+  free_all_locked();
+}
+}  // namespace devcache
 
 bool g_inited = false;
 void ensure_init() {
@@ -207,7 +274,18 @@ struct Run {
   // multiply-adds (x2) of the update launch of step j on real entries only;
   // f64 receives the part done in float64 (all of it for double runs, the V
   // part in mixed runs)
-  double update_flops(int j, int64_t s_valid, double* f64) const {
+  std::vector<int64_t> cum_nvalid;  // per J tile: real columns before it (built on demand)
+  double update_flops(int j, int64_t s_valid, double* f64) {
+    if (cum_nvalid.size() != rt.size()) {
+      cum_nvalid.assign(rt.size(), 0);
+      for (const ProbDesc& p : pd) {
+        int64_t acc = 0;
+        for (int k = 0; k < p.T; ++k) {
+          cum_nvalid[p.first + k] = acc;
+          acc += rt[p.first + k].nvalid;
+        }
+      }
+    }
     double f = 0.0, fv = 0.0;
     for (int64_t t = upd_off[j]; t < upd_off[j] + upd_n[j]; ++t) {
       const WorkItem it = items[t];
@@ -215,8 +293,7 @@ struct Run {
       const RowTile<T>& ri = rt[p.first + it.tile];
       const RowTile<T>& rj = rt[p.first + j];
       const double Kv = (ri.vt64 && rj.vt64) ? (double)s_valid : 0.0;
-      double K = Kv;
-      for (int k = 0; k < j; ++k) K += rt[p.first + k].nvalid;
+      const double K = Kv + (double)cum_nvalid[p.first + j];
       const double rows = ri.nvalid, cols = rj.nvalid;
       const double pairs = (ri.is_j && it.tile == j) ? rows * (rows + 1) / 2 : rows * cols;
       f += 2.0 * pairs * K;
@@ -296,7 +373,7 @@ struct lma_state {
   double qsum = 0, ld_R = 0, ld_ss = 0, ld_dd = 0, ydg = 0, lml = 0;
 
   ~lma_state() {
-    if (ar.base) (void)hipFree(ar.base);
+    if (ar.base) devcache::put(ar.base, (size_t)ar.cap);
   }
   bool mixed() const { return precision == LMA_MIXED; }
   template <typename T>
@@ -620,10 +697,8 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     throw Err{LMA_E_NOMEM, buf};
   }
   {
-    void* mem = nullptr;
-    hipError_t e = hipMalloc(&mem, (size_t)f.ar.cap);
-    if (e != hipSuccess || !mem) {
-      (void)hipGetLastError();
+    void* mem = devcache::get((size_t)f.ar.cap);
+    if (!mem) {
       char buf[160];
       snprintf(buf, sizeof buf, "hipMalloc of %lld bytes failed", (long long)f.ar.cap);
       throw Err{LMA_E_NOMEM, buf};
@@ -1137,21 +1212,19 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   const int64_t o_terms = ar.reserve(sizeof(GemmTerm<TW>) * std::max<size_t>(terms.size(), 1));
   const int64_t o_outs = ar.reserve(sizeof(GemmOut) * std::max<size_t>(outs.size(), 1));
   ar.cap = ar.used;
-  void* mem = nullptr;
-  if (hipMalloc(&mem, (size_t)ar.cap) != hipSuccess || !mem) {
-    (void)hipGetLastError();
-    throw Err{LMA_E_NOMEM, "hipMalloc of the prediction workspace failed"};
-  }
+  void* mem = devcache::get((size_t)ar.cap);
+  if (!mem) throw Err{LMA_E_NOMEM, "device allocation of the prediction workspace failed"};
   struct Guard {
     void* p;
+    size_t bytes;
     hipStream_t s;
     ~Guard() {
       if (p) {
         (void)hipStreamSynchronize(s);
-        (void)hipFree(p);
+        devcache::put(p, bytes);
       }
     }
-  } guard{mem, st};
+  } guard{mem, (size_t)ar.cap, st};
   build(reinterpret_cast<char*>(mem));
   {
     char* mp = at<char>(ar, o_meta);
@@ -1373,6 +1446,8 @@ int64_t lma_failed_block(void) { return g_failed; }
 const char* lma_version(void) { return "lma-gfx950 0.1"; }
 
 void lma_profile_enable(int on) { prof::on = on != 0; }
+
+void lma_release_cache(void) { devcache::release(); }
 
 lma_status lma_profile_read(lma_profile* out, int reset) {
   if (!out) {
