@@ -190,17 +190,80 @@ def fit(X, y, block_ptr, S, B, log_hyp, prior_mean=0.0, precision="fp64", mem_bu
     return State(h, inp.problem.M)
 
 
-def lml(X, y, block_ptr, S, B, log_hyp, prior_mean=0.0, precision="fp64", grad=False, stream=None):
+def lml(X, y, block_ptr, S, B, log_hyp, prior_mean=0.0, precision="fp64", grad=False, mem_budget=0,
+        stream=None):
     """lma_lml: log marginal likelihood (and its gradient in log_hyp)."""
-    import torch
     load()
-    inp = _Inputs(X, y, block_ptr, S, B, log_hyp, prior_mean, precision, 0)
+    inp = _Inputs(X, y, block_ptr, S, B, log_hyp, prior_mean, precision, mem_budget)
+    return _lml_call(inp, grad, stream)
+
+
+def _lml_call(inp, grad, stream=None):
+    import torch
     out = ctypes.c_double()
     g = np.zeros(inp.problem.d + 2) if grad else None
     _check(_lib.lma_lml(ctypes.byref(inp.problem), ctypes.byref(out),
                         g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if grad else None,
                         _stream(torch, stream)))
     return (out.value, g) if grad else out.value
+
+
+class LmlProblem:
+    """Training data of an LMA likelihood, uploaded once; call with log_hyp.
+
+    log_hyp = [log l_1..log l_d, log sigma_s^2, log sigma_n^2]."""
+
+    def __init__(self, X, y, block_ptr, S, B, prior_mean=0.0, precision="fp64", mem_budget=0):
+        load()
+        d = np.asarray(X.shape)[1] if hasattr(X, "shape") else len(X[0])
+        self._inp = _Inputs(X, y, block_ptr, S, B, np.zeros(int(d) + 2), prior_mean, precision, mem_budget)
+        self.d = int(d)
+
+    def __call__(self, log_hyp, grad=True, stream=None):
+        lh = np.ascontiguousarray(np.asarray(log_hyp, dtype=np.float64).reshape(-1))
+        if lh.shape[0] != self.d + 2:
+            raise ValueError(f"log_hyp must have d+2 = {self.d + 2} entries")
+        self._inp.lh = lh
+        self._inp.problem.log_hyp = lh.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        return _lml_call(self._inp, grad, stream)
+
+    @classmethod
+    def from_problem(cls, p, precision="fp64", **kw):
+        return cls(p.X, p.y, p.block_ptr, p.S, p.B, p.prior_mean, precision=precision, **kw)
+
+
+_LML_FN = None
+
+
+def _lml_function():
+    global _LML_FN
+    if _LML_FN is None:
+        import torch
+
+        class LMALogML(torch.autograd.Function):
+            """LML(log_hyp) with the hand-written adjoint as its backward.
+
+            LMALogML.apply(log_hyp, problem) -> 0-d tensor; problem is an LmlProblem."""
+
+            @staticmethod
+            def forward(ctx, log_hyp, problem):
+                val, g = problem(log_hyp.detach().to("cpu", torch.float64).numpy(), grad=True)
+                ctx.save_for_backward(torch.as_tensor(g, dtype=log_hyp.dtype, device=log_hyp.device))
+                return torch.tensor(val, dtype=log_hyp.dtype, device=log_hyp.device)
+
+            @staticmethod
+            def backward(ctx, grad_out):
+                (g,) = ctx.saved_tensors
+                return grad_out * g, None
+
+        _LML_FN = LMALogML
+    return _LML_FN
+
+
+def __getattr__(name):
+    if name == "LMALogML":
+        return _lml_function()
+    raise AttributeError(name)
 
 
 def fit_problem(p, precision="fp64", **kw):

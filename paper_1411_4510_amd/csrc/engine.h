@@ -28,11 +28,14 @@ constexpr int TB = 128;     // tile edge
 constexpr int NT = 256;     // threads per workgroup (4 wave64)
 constexpr int DIAG_LD = TB + 1;
 
-enum Src : int32_t { SRC_KERNEL = 0, SRC_EXPLICIT = 1, SRC_CVEC = 2 };
+// SRC_IDENT: the right-hand-side rows are rows kbeg*TB .. kbeg*TB+127 of the
+// identity, so the solve produces the matching rows of L^-T (an explicit
+// inverse factor); such a row is zero left of column tile kbeg.
+enum Src : int32_t { SRC_KERNEL = 0, SRC_EXPLICIT = 1, SRC_CVEC = 2, SRC_IDENT = 3 };
 
 template <typename T>
 struct RowTile {
-  T* panel;          // row r of this row tile at panel + r*ld; column tile k at +k*TB
+  T* panel;          // row r of this row tile at panel + r*ld; column tile k at +(k-kbeg)*TB
   int64_t ld;
   const T* vt;       // whitened support rows of the tile's points (row r at vt + r*vld) or null
   const T* xs;       // length-scaled coordinates of the tile's points ([r][d]) or null
@@ -45,6 +48,8 @@ struct RowTile {
   int32_t nstore;    // rows physically stored (loads beyond read 0, stores skipped)
   int32_t src;       // Src
   int32_t is_j;      // 1 for rows of the matrix being factored
+  int32_t kbeg;      // first column tile stored (the row is zero to its left); 0 except SRC_IDENT
+  int32_t pad_;
 };
 
 struct ProbDesc {
@@ -88,12 +93,14 @@ void launch_diag(const StepArgs<T>& a, const int32_t* plist, int np, hipStream_t
 template <typename T>
 void launch_trsm(const StepArgs<T>& a, hipStream_t st);
 
-// Batched float64-accumulating GEMM over tiles: item i computes
-//   acc = sum over its terms t of A_t[:, k0:k1] B_t[:, k0:k1]^T   (128 x 128)
-// and writes (or adds) acc into its output tile.  A_t and B_t rows are
-// contiguous in k; rows past anr / bnr read as zero.  Used for the global
-// summary (sum over windows of Z^T Z, Z^T z, z^T z) and for the per-test-point
-// prediction sums.
+// Batched float64-accumulating GEMM over tiles: output tile o computes
+//   acc = sum_{t in [tneg, t1)} A_t B_t^T - sum_{t in [t0, tneg)} A_t B_t^T
+// over the column range [k0, k1) of each term (A_t, B_t rows contiguous in k;
+// the tile is 128 x 128) and writes
+//   out = (accumulate ? out : 0) + beta * c + alpha * acc
+// on its valid rows / columns (c optional).  Operand rows at or past anr / bnr
+// are read from row 0, so an output tile must not store rows >= anr or
+// columns >= bnr of any of its terms.
 template <typename T>
 struct GemmTerm {
   const T* a; int64_t lda; int32_t anr;
@@ -102,10 +109,26 @@ struct GemmTerm {
 };
 struct GemmOut {
   double* out; int64_t ld;
+  const double* c; int64_t ldc;   // addend (scaled by beta) or null
+  double alpha, beta;
   int32_t rows, cols;    // valid rows / columns of the output tile
   int32_t accumulate;    // 1: add to the output, 0: overwrite
-  int32_t t0, t1;        // terms [t0, t1)
+  int32_t t0, tneg, t1;  // terms [t0, tneg) are subtracted, [tneg, t1) added
 };
+inline GemmOut gemm_out(double* out, int64_t ld, int rows, int cols, int accumulate, int t0) {
+  GemmOut o;
+  o.out = out;
+  o.ld = ld;
+  o.c = nullptr;
+  o.ldc = 0;
+  o.alpha = 1.0;
+  o.beta = 0.0;
+  o.rows = rows;
+  o.cols = cols;
+  o.accumulate = accumulate;
+  o.t0 = o.tneg = o.t1 = t0;
+  return o;
+}
 template <typename T>
 void launch_tile_gemm(const GemmTerm<T>* terms, const GemmOut* outs, int nout, hipStream_t st);
 

@@ -1,142 +1,11 @@
 // Device kernels of the tiled Cholesky / triangular-solve engine (gfx950).
-//
-// Work decomposition: a workgroup of 4 wave64 computes one 128x128 output
-// tile; wave (wr, wc) owns the 64x64 quadrant (wr, wc) as 4x4 MFMA 16x16
-// sub-tiles.  Operand fragments are read straight from HBM/L2 in the MFMA
-// 16x16x4 input layout (lane l supplies row l%16 and four consecutive k
-// values starting at 4*(l/16)); the four MFMA k-steps of a 16-wide k chunk
-// consume those four values, so each lane issues one contiguous 4-element
-// load per sub-tile row per chunk and the next chunk is prefetched while the
-// current one runs on the matrix cores.
+// The MFMA tile core (operand layout, prefetch pipeline) is in mfma_core.h.
 #include "engine.h"
+#include "mfma_core.h"
 
 #include <type_traits>
 
 namespace lma {
-
-typedef double dv4 __attribute__((ext_vector_type(4)));
-typedef float fv4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct V4;
-template <>
-struct V4<double> { typedef dv4 type; };
-template <>
-struct V4<float> { typedef fv4 type; };
-
-template <typename Tc>
-struct Mfma;
-template <>
-struct Mfma<double> {
-  typedef dv4 acc;
-  __device__ static inline acc op(double a, double b, acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  // register v of lane l holds row (l/16) + 4v, column l%16 of the 16x16 tile
-  __device__ static inline int row(int l, int v) { return (l >> 4) + 4 * v; }
-};
-template <>
-struct Mfma<float> {
-  typedef fv4 acc;
-  __device__ static inline acc op(float a, float b, acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  // register v of lane l holds row 4*(l/16) + v, column l%16 of the 16x16 tile
-  __device__ static inline int row(int l, int v) { return 4 * (l >> 4) + v; }
-};
-
-__device__ inline double k_exp(double x) { return exp(x); }
-__device__ inline float k_exp(float x) { return expf(x); }
-__device__ inline double k_sqrt(double x) { return sqrt(x); }
-__device__ inline float k_sqrt(float x) { return sqrtf(x); }
-
-// Workgroups are dealt round-robin to the 8 XCDs; remap so that consecutive
-// work items (tiles of the same problem, which share the B operand) land on
-// the same XCD and its L2.  The grid is padded to a multiple of 8.
-__device__ inline int xcd_logical(int bid, int nb) {
-  const int per = nb >> 3;
-  return (bid & 7) * per + (bid >> 3);
-}
-
-// acc[ra][rb] += A[arow0 + 16 ra + i, k] * Bm[brow0 + 16 rb + j, k] over k in [k0, k1).
-// Rows at or past anr / bnr are read from row 0 instead (always a valid
-// address): they only feed output rows / columns that the callers either do
-// not store or overwrite with their exact value (padding).  Loads are
-// unconditional and rotate through PF+1 register slots, so the chunk in use
-// never waits for the chunks in flight.
-// PERMA feeds the A rows of each 16-row sub-tile in the order r(4a+b) = a+4b, which
-// turns the float32 16x16 output layout into the float64 one (row l/16 + 4v).
-template <typename Tin, typename Tc, bool PERMA = false, int PF = 2>
-__device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
-                                          const Tin* __restrict__ A, int64_t lda, int anr,
-                                          const Tin* __restrict__ Bm, int64_t ldb, int bnr,
-                                          int k0, int k1, int arow0, int brow0, int lane) {
-  typedef typename V4<Tin>::type vin;
-  const int r16 = lane & 15, kq = (lane >> 4) << 2;
-  const Tin* pa[4];
-  const Tin* pb[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int ra = arow0 + t * 16 + (PERMA ? ((r16 >> 2) | ((r16 & 3) << 2)) : r16);
-    pa[t] = A + (int64_t)(ra < anr ? ra : 0) * lda + k0 + kq;
-    const int rb = brow0 + t * 16 + r16;
-    pb[t] = Bm + (int64_t)(rb < bnr ? rb : 0) * ldb + k0 + kq;
-  }
-  const int nc = (k1 - k0) >> 4;
-  if (nc <= 0) return;
-  vin sa[PF + 1][4], sb[PF + 1][4];
-  // chunk x lives in slot x % (PF+1)
-#define LMA_LOAD_CHUNK(X, SLOT)                                \
-  {                                                            \
-    const int off_ = (X) << 4;                                 \
-    const int slot_ = (SLOT);                                  \
-    _Pragma("unroll") for (int u_ = 0; u_ < 4; ++u_) {         \
-      sa[slot_][u_] = *(const vin*)(pa[u_] + off_);            \
-      sb[slot_][u_] = *(const vin*)(pb[u_] + off_);            \
-    }                                                          \
-  }
-#define LMA_MMA_SLOT(SLOT)                                                                 \
-  {                                                                                        \
-    const int slot_ = (SLOT);                                                              \
-    _Pragma("unroll") for (int e = 0; e < 4; ++e) {                                        \
-      _Pragma("unroll") for (int ra = 0; ra < 4; ++ra) {                                   \
-        _Pragma("unroll") for (int rb = 0; rb < 4; ++rb) {                                 \
-          acc[ra][rb] = Mfma<Tc>::op((Tc)sa[slot_][ra][e], (Tc)sb[slot_][rb][e], acc[ra][rb]); \
-        }                                                                                  \
-      }                                                                                    \
-    }                                                                                      \
-  }
-#pragma unroll
-  for (int p = 0; p < PF; ++p)
-    if (p < nc) LMA_LOAD_CHUNK(p, p)
-  int c = 0;
-  // steady state: every prefetch is in range, no branches in the body
-  for (; c + 2 * PF < nc; c += PF + 1) {
-#pragma unroll
-    for (int q = 0; q <= PF; ++q) {
-      LMA_LOAD_CHUNK(c + q + PF, (q + PF) % (PF + 1))
-      LMA_MMA_SLOT(q)
-    }
-  }
-  // tail: at most 2*PF+1 chunks, slots known at compile time
-#pragma unroll
-  for (int t = 0; t <= 2 * PF; ++t) {
-    if (c + t < nc) {
-      if (c + t + PF < nc) LMA_LOAD_CHUNK(c + t + PF, (t + PF) % (PF + 1))
-      LMA_MMA_SLOT(t % (PF + 1))
-    }
-  }
-#undef LMA_LOAD_CHUNK
-#undef LMA_MMA_SLOT
-}
-
-template <typename Tc>
-__device__ inline void zero_acc(typename Mfma<Tc>::acc (&acc)[4][4]) {
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (typename Mfma<Tc>::acc){Tc(0), Tc(0), Tc(0), Tc(0)};
-}
 
 // ---------------------------------------------------------------------------
 // update: C_ij = K_ij - V_i V_j^T - sum_{k<j} L_ik L_jk^T for every item (p, i)
@@ -162,13 +31,16 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
   const TK* vj = MIXED ? (const TK*)rj.vt64 : (const TK*)rj.vt;
   if (vi != nullptr && vj != nullptr && a.vlen > 0)
     wave_gemm<TK, TK>(accv, vi, a.vld, ri.nvalid, vj, a.vld, rj.nvalid, 0, a.vlen, wr * 64, wc * 64, lane);
-  if (a.j > 0) {
+  // factor columns kb .. j-1 (a row is zero left of its kbeg)
+  const int kb = ri.kbeg > rj.kbeg ? ri.kbeg : rj.kbeg;
+  if (a.j > kb) {
+    const T* pa = ri.panel + (int64_t)(kb - ri.kbeg) * TB;
+    const T* pb = rj.panel + (int64_t)(kb - rj.kbeg) * TB;
     if constexpr (MIXED)
-      wave_gemm<T, T, true>(accl, ri.panel, ri.ld, ri.nstore, rj.panel, rj.ld, rj.nstore, 0, a.j * TB, wr * 64,
-                            wc * 64, lane);
+      wave_gemm<T, T, true>(accl, pa, ri.ld, ri.nstore, pb, rj.ld, rj.nstore, 0, (a.j - kb) * TB, wr * 64, wc * 64,
+                            lane);
     else
-      wave_gemm<T, T>(accv, ri.panel, ri.ld, ri.nstore, rj.panel, rj.ld, rj.nstore, 0, a.j * TB, wr * 64, wc * 64,
-                      lane);
+      wave_gemm<T, T>(accv, pa, ri.ld, ri.nstore, pb, rj.ld, rj.nstore, 0, (a.j - kb) * TB, wr * 64, wc * 64, lane);
   }
 
   const int d = a.d;
@@ -187,7 +59,9 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
   __syncthreads();
   const bool diag = ri.is_j && (it.tile == a.j);
   const TK sf2 = (TK)a.sf2, sn2 = (TK)a.sn2;
-  T* out = ri.panel + (int64_t)a.j * TB;
+  T* out = ri.panel + (int64_t)(a.j - ri.kbeg) * TB;
+  const bool ident = ri.src == SRC_IDENT;
+  const bool ident_here = ident && ri.kbeg == a.j;
 #pragma unroll
   for (int rs = 0; rs < 4; ++rs) {
 #pragma unroll
@@ -197,7 +71,9 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
         const int row = wr * 64 + rs * 16 + Mfma<TK>::row(lane, v);
         const int col = wc * 64 + cs * 16 + (lane & 15);
         TK kv = TK(0);
-        if (row < ri.nvalid && col < rj.nvalid) {
+        if (ident) {
+          kv = (ident_here && row == col) ? TK(1) : TK(0);  // exact at padding too
+        } else if (row < ri.nvalid && col < rj.nvalid) {
           if (kern) {
             TK s = TK(0);
             for (int t = 0; t < d; ++t) {
@@ -330,7 +206,7 @@ __global__ __launch_bounds__(NT) void k_trsm(StepArgs<T> a) {
   const ProbDesc pd = a.pd[it.p];
   const RowTile<T> ri = a.rt[pd.first + it.tile];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
-  T* C = ri.panel + (int64_t)a.j * TB;
+  T* C = ri.panel + (int64_t)(a.j - ri.kbeg) * TB;
   const T* Li = a.invdiag + pd.invdiag_off + (int64_t)a.j * TB * TB;
   typename Mfma<T>::acc acc[4][4];
   zero_acc<T>(acc);
@@ -361,9 +237,21 @@ __global__ __launch_bounds__(NT) void k_tile_gemm(const GemmTerm<T>* __restrict_
   typename Mfma<double>::acc acc[4][4];
   zero_acc<double>(acc);
   for (int t = o.t0; t < o.t1; ++t) {
+    if (t == o.tneg && t > o.t0) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = -acc[a][b];
+    }
     const GemmTerm<T> tm = terms[t];
     wave_gemm<T, double>(acc, tm.a, tm.lda, tm.anr, tm.b, tm.ldb, tm.bnr, tm.k0, tm.k1, wr * 64, wc * 64,
                          lane);
+  }
+  if (o.tneg == o.t1 && o.t1 > o.t0) {  // only subtracted terms
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = -acc[a][b];
   }
 #pragma unroll
   for (int rs = 0; rs < 4; ++rs)
@@ -375,7 +263,9 @@ __global__ __launch_bounds__(NT) void k_tile_gemm(const GemmTerm<T>* __restrict_
         const int col = wc * 64 + cs * 16 + (lane & 15);
         if (row < o.rows && col < o.cols) {
           double* q = o.out + (int64_t)row * o.ld + col;
-          *q = o.accumulate ? *q + acc[rs][cs][v] : acc[rs][cs][v];
+          double r = o.alpha * acc[rs][cs][v];
+          if (o.c) r += o.beta * o.c[(int64_t)row * o.ldc + col];
+          *q = o.accumulate ? *q + r : r;
         }
       }
 }

@@ -1,0 +1,113 @@
+"""Gradient of the log marginal likelihood on the GPU (lma_lml with grad):
+against the oracle's adjoint, against central finite differences of the GPU
+likelihood (step 1e-5, float64), under forced window chunking, through the
+autograd Function, and at the n=131072 workload against stored oracle values."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import lma as olma
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+TOL = {"fp64": 1e-9, "mixed": 1e-4}
+
+CASES = [
+    dict(seed=41, n=150, d=2, M=5, s=10, B=2),
+    dict(seed=7, n=300, d=3, M=6, s=37, B=1, uneven=(20, 80)),
+    dict(seed=9, n=260, d=2, M=4, s=20, B=0),
+    dict(seed=11, n=400, d=3, M=7, s=45, B=3, uneven=(30, 90)),
+    dict(seed=5, n=3000, d=5, M=7, s=200, B=2, uneven=(200, 700)),
+    dict(seed=6, n=2400, d=4, M=6, s=130, B=5, uneven=(150, 600)),
+]
+
+
+def rel(a, b):
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def problem(case):
+    return synth.make_random(n_u=0, prior_mean=0.2, **case)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("ci", range(len(CASES)))
+def test_grad_matches_oracle(lib, ci, prec):
+    case = CASES[ci]
+    p = problem(case)
+    print(f"case {case} {prec}", flush=True)
+    lv, go = olma.lml_grad(p)
+    l, g = lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, precision=prec, grad=True)
+    eg, el = rel(g, go), abs(l - lv) / abs(lv)
+    print(f"  rel err grad {eg:.2e} lml {el:.2e}", flush=True)
+    assert el <= TOL[prec]
+    assert eg <= TOL[prec]
+
+
+def test_grad_central_differences(lib):
+    """Central differences of the GPU likelihood, step 1e-5 in each log-hyperparameter."""
+    p = problem(CASES[4])
+    prob = lib.LmlProblem.from_problem(p, precision="fp64")
+    _, g = prob(p.log_hyp)
+    h = 1e-5
+    fd = np.zeros_like(g)
+    for q in range(p.d + 2):
+        e = np.zeros_like(p.log_hyp)
+        e[q] = h
+        fd[q] = (prob(p.log_hyp + e, grad=False) - prob(p.log_hyp - e, grad=False)) / (2 * h)
+    print(f"  grad {g}\n  fd   {fd}\n  rel {rel(g, fd):.2e}", flush=True)
+    assert rel(g, fd) <= 1e-6
+
+
+def test_grad_chunked_equals_single(lib, monkeypatch):
+    """Windows processed in many small chunks give the same gradient bit for bit."""
+    p = problem(CASES[5])
+    l1, g1 = lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, grad=True)
+    monkeypatch.setenv("LMA_GRAD_CHUNK_BYTES", "1")
+    l2, g2 = lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, grad=True)
+    assert l1 == l2
+    assert np.array_equal(g1, g2)
+
+
+def test_grad_deterministic(lib):
+    p = problem(CASES[4])
+    r = [lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, grad=True) for _ in range(2)]
+    assert r[0][0] == r[1][0]
+    assert np.array_equal(r[0][1], r[1][1])
+
+
+def test_autograd_function(lib):
+    import torch
+    p = problem(CASES[1])
+    prob = lib.LmlProblem.from_problem(p)
+    th = torch.tensor(p.log_hyp, dtype=torch.float64, requires_grad=True)
+    out = lib.LMALogML.apply(th, prob)
+    (2.0 * out).backward()
+    lv, go = olma.lml_grad(p)
+    assert abs(out.item() - lv) <= 1e-9 * abs(lv)
+    assert rel(th.grad.numpy() / 2.0, go) <= 1e-9
+
+
+def test_grad_n131072_against_stored_oracle(lib):
+    path = os.path.join(HERE, "golden", "cfg3_oracle.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    with open(path) as f:
+        gold = json.load(f)
+    p = synth.make_config(3)
+    dg = p.digest()
+    for k, v in gold["digest"].items():
+        if isinstance(v, float):
+            assert abs(dg[k] - v) <= 1e-9 * max(1.0, abs(v)), k
+        else:
+            assert dg[k] == v, k
+    for prec in ("fp64", "mixed"):
+        print(f"case cfg3 n={p.n} {prec}", flush=True)
+        l, g = lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, precision=prec, grad=True)
+        eg, el = rel(g, gold["grad"]), abs(l - gold["lml"]) / abs(gold["lml"])
+        print(f"  rel err grad {eg:.2e} lml {el:.2e}", flush=True)
+        assert max(eg, el) <= TOL[prec]
