@@ -5,7 +5,8 @@ Workload (the n=524288 configuration): d = 21 inputs from a mixture of 32
 Gaussians, M = 256 capacity-bounded k-means blocks (1024..3072 points),
 Markov order B = 3, |S| = 1024, 65536 test points.  One step = lma_fit
 (summaries, global solve, LML) + lma_predict (mean and variance) on inputs
-already resident in HBM.
+already resident in HBM.  The log marginal likelihood with its gradient
+(lma_lml with grad) is timed separately at the same shape.
 
 Prints one JSON line.  `value` is the float64 fit+predict time per step
 (seconds, lower is better); the mixed-precision time, its speedup and its
@@ -130,6 +131,8 @@ def main():
     ap.add_argument("--modes", default="fp64,mixed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-lml", action="store_true", help="skip the separate LML-rate measurement")
+    ap.add_argument("--no-grad", action="store_true", help="skip the LML+gradient measurement")
+    ap.add_argument("--grad-evals", type=int, default=1, help="timed LML+gradient evaluations per precision")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--small", action="store_true", help="n=65536 workload (quick check)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -205,6 +208,33 @@ def main():
         torch.cuda.synchronize()
         lml_rate = 1.0 / (time.perf_counter() - t1)
 
+    # LML + gradient evaluations per second (adjoint of the same computation)
+    grad_res = {}
+    if not args.no_grad:
+        for prec in [m for m in args.modes.split(",") if m]:
+            prob = lma.LmlProblem(X, y, p.block_ptr, S, p.B, p.prior_mean, precision=prec)
+            prob(p.log_hyp)
+            log(f"{prec} LML+grad warmup done")
+            lma.profile_enable(True)
+            lma.profile_read(reset=True)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(args.grad_evals):
+                val, g = prob(p.log_hyp)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) / args.grad_evals
+            gprof = lma.profile_read(reset=True)
+            lma.profile_enable(False)
+            grad_res[prec] = {"evals_per_s": 1.0 / dt, "s_per_eval": dt, "lml": val, "grad": g.tolist(),
+                              "profile": gprof}
+            log(f"{prec} LML+grad: {dt:.3f} s/eval, profile {gprof}")
+        if "fp64" in grad_res and "mixed" in grad_res:
+            ga, gb = np.array(grad_res["mixed"]["grad"]), np.array(grad_res["fp64"]["grad"])
+            grad_res["mixed"]["rel_err_vs_fp64"] = {
+                "grad": float(np.linalg.norm(ga - gb) / np.linalg.norm(gb)),
+                "lml": abs(grad_res["mixed"]["lml"] - grad_res["fp64"]["lml"]) / abs(grad_res["fp64"]["lml"])}
+            grad_res["mixed"]["speedup_vs_fp64"] = grad_res["fp64"]["s_per_eval"] / grad_res["mixed"]["s_per_eval"]
+
     f_fit, f_pred = algorithmic_flops(p)
     head = "fp64" if "fp64" in res else list(res)[0]
     prof = res[head]["profile"]
@@ -242,6 +272,7 @@ def main():
         "fp64": res.get("fp64"),
         "mixed": res.get("mixed"),
         "lml_evals_per_s_fp64": lml_rate,
+        "lml_grad": grad_res or None,
         "alg_flops": {"fit": f_fit, "predict": f_pred},
         "roofline": roofline,
     }

@@ -104,9 +104,15 @@ lma_status lma_predict(lma_state *f, int64_t n_u, const double *U, const int64_t
 
 /*
  * Log marginal likelihood log N(y; mu, Sigma_bar_DD) of the LMA prior
- * (through the matrix inversion lemma of Eq. (5)), written to *lml (host).
- * If grad (host, [d+2]) is not NULL it receives the gradient with respect to
- * log_hyp.  Errors as for lma_fit.
+ * (through the matrix inversion lemma of Eq. (5) and the block factor of
+ * Lemma 1), written to *lml (host).  If grad (host, [d+2]) is not NULL it
+ * receives the gradient with respect to log_hyp = (log l_1..log l_d,
+ * log sigma_s^2, log sigma_n^2), from the reverse-mode adjoint of the same
+ * computation (the prior mean is held fixed).  The gradient pass processes
+ * the windows in chunks whose workspace stays under the part of
+ * mem_budget_bytes the fitted state leaves (at least 256 MB; 16 GB when
+ * mem_budget_bytes is 0).  Synchronises the stream.  Errors as for lma_fit;
+ * LMA_E_NOT_PD also for a non-finite gradient.
  */
 lma_status lma_lml(const lma_problem *p, double *lml, double *grad, hipStream_t stream);
 
@@ -134,7 +140,8 @@ int64_t lma_failed_block(void);
  * (which synchronise anyway).  update_alg_flops counts the multiply-adds of
  * the update launches on real entries only (no tile padding), 2 flops each:
  * the Cholesky updates, the Q = V^T V correction of the residual and the
- * right-hand-side updates.  Not thread safe; for single-threaded use.
+ * right-hand-side updates.  Tile GEMMs and gradient contractions are timed in
+ * their own fields (not in other_ms).  Not thread safe; for single-threaded use.
  */
 typedef struct {
   double update_ms;          /* summed device time of update launches */
@@ -144,7 +151,13 @@ typedef struct {
   double update_alg_flops;   /* algorithmic flops of the timed update launches */
   double update_alg_flops_f64; /* the part of them done on float64 matrix cores */
   int64_t update_launches;
-  int64_t other_launches;
+  int64_t other_launches;    /* launches counted in other_ms */
+  double gemm_ms;            /* batched tile GEMMs (summaries, prediction sums, gradient products) */
+  double gemm_alg_flops;     /* 2 x multiply-adds on their valid output entries */
+  double contract_ms;        /* gradient contractions (adjoint tile x covariance derivatives) */
+  double contract_alg_flops; /* 2 x multiply-adds of their tile products on valid entries */
+  int64_t gemm_launches;
+  int64_t contract_launches;
 } lma_profile;
 
 void lma_profile_enable(int on);

@@ -53,6 +53,9 @@ class Profile(ctypes.Structure):
         ("trsm_ms", ctypes.c_double), ("other_ms", ctypes.c_double),
         ("update_alg_flops", ctypes.c_double), ("update_alg_flops_f64", ctypes.c_double),
         ("update_launches", ctypes.c_int64), ("other_launches", ctypes.c_int64),
+        ("gemm_ms", ctypes.c_double), ("gemm_alg_flops", ctypes.c_double),
+        ("contract_ms", ctypes.c_double), ("contract_alg_flops", ctypes.c_double),
+        ("gemm_launches", ctypes.c_int64), ("contract_launches", ctypes.c_int64),
     ]
 
     def as_dict(self):

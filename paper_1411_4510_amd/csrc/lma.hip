@@ -148,6 +148,16 @@ void flush() {
         break;
       case DIAG: acc.diag_ms += ms; break;
       case TRSM: acc.trsm_ms += ms; break;
+      case GEMM:
+        acc.gemm_ms += ms;
+        acc.gemm_alg_flops += r.flops;
+        acc.gemm_launches += 1;
+        break;
+      case CONTRACT:
+        acc.contract_ms += ms;
+        acc.contract_alg_flops += r.flops;
+        acc.contract_launches += 1;
+        break;
       default:
         acc.other_ms += ms;
         acc.other_launches += 1;
@@ -467,10 +477,10 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   run_with_stride(f.runS, f.ptr<double>(f.o_Lss_inv), (int)M, 0);
   if (mixed) {
     run_with_stride(f.runW32, f.ptr<float>(f.o_win_inv), 0, (int)sp);
-    prof::timed(prof::OTHER, 0.0, st, [&] { launch_tile_gemm<float>(reinterpret_cast<const GemmTerm<float>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
+    prof::timed(prof::GEMM, prof::on ? gemm_flops(f.sum32, f.sumout, 0, (int64_t)f.sumout.size()) : 0.0, st, [&] { launch_tile_gemm<float>(reinterpret_cast<const GemmTerm<float>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
   } else {
     run_with_stride(f.runW64, f.ptr<double>(f.o_win_inv), 0, (int)sp);
-    prof::timed(prof::OTHER, 0.0, st, [&] { launch_tile_gemm<double>(reinterpret_cast<const GemmTerm<double>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
+    prof::timed(prof::GEMM, prof::on ? gemm_flops(f.sum64, f.sumout, 0, (int64_t)f.sumout.size()) : 0.0, st, [&] { launch_tile_gemm<double>(reinterpret_cast<const GemmTerm<double>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
   }
   HIPCHK(hipGetLastError());
   {
@@ -1002,7 +1012,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   for (int dl = 0; dl <= f.B; ++dl) {
     const int a0 = dl_split[dl], a1 = dl_split[dl + 1];
     if (a1 > a0)
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_tile_gemm<TW>(at<GemmTerm<TW>>(ar, o_terms), at<GemmOut>(ar, o_outs) + a0, a1 - a0, st); });
+      prof::timed(prof::GEMM, prof::on ? gemm_flops(terms, outs, a0, a1) : 0.0, st, [&] { launch_tile_gemm<TW>(at<GemmTerm<TW>>(ar, o_terms), at<GemmOut>(ar, o_outs) + a0, a1 - a0, st); });
     HIPCHK(hipGetLastError());
   }
   {

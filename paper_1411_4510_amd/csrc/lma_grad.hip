@@ -655,8 +655,21 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st) {
   double* ldg = at<double>(ar, o_stat) + 8;
   auto gemm_d = [&](const GemmBatch& b) {
     if (b.o1 > b.o0)
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_tile_gemm<double>(dd_terms, douts_d + b.o0, (int)(b.o1 - b.o0), st); });
+      prof::timed(prof::GEMM, prof::on ? gemm_flops(d_terms, outs_d, b.o0, b.o1) : 0.0, st,
+                  [&] { launch_tile_gemm<double>(dd_terms, douts_d + b.o0, (int)(b.o1 - b.o0), st); });
     HIPCHK(hipGetLastError());
+  };
+  // 2 x multiply-adds of the tile products of contraction items [i0, i1) on valid entries
+  auto contract_flops = [&](int64_t i0, int64_t i1) {
+    double fl = 0.0;
+    for (int64_t i = i0; i < i1; ++i) {
+      const DcItem& it = items[i];
+      double k = 0.0;
+      for (int t = it.x0; t < it.x1; ++t) k += x_terms[t].k1 - x_terms[t].k0;
+      for (int t = it.t0; t < it.t1; ++t) k += d_terms[t].k1 - d_terms[t].k0;
+      fl += 2.0 * it.nr * it.nc * k;
+    }
+    return fl;
   };
   auto contract = [&](int64_t i0, int64_t i1) {
     DcArgs<TW> a;
@@ -668,7 +681,8 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st) {
     a.sf2 = f.sf2;
     a.sn2 = f.sn2;
     a.partial = part + i0 * ncomp;
-    if (i1 > i0) prof::timed(prof::OTHER, 0.0, st, [&] { launch_dcontract<TW>(a, st); });
+    if (i1 > i0)
+      prof::timed(prof::CONTRACT, prof::on ? contract_flops(i0, i1) : 0.0, st, [&] { launch_dcontract<TW>(a, st); });
     HIPCHK(hipGetLastError());
   };
 
@@ -694,7 +708,7 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st) {
   for (int c = 0; c < nchunk; ++c) {
     solve_steps<TW>(runX[c], wininv, f, ldg, stat, st);
     if (c2[c].o1 > c2[c].o0)
-      prof::timed(prof::OTHER, 0.0, st, [&] {
+      prof::timed(prof::GEMM, prof::on ? gemm_flops(tw_terms, outs_tw, c2[c].o0, c2[c].o1) : 0.0, st, [&] {
         launch_tile_gemm<TW>(dtw_terms, douts_tw + c2[c].o0, (int)(c2[c].o1 - c2[c].o0), st);
       });
     HIPCHK(hipGetLastError());

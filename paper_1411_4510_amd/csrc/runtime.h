@@ -64,7 +64,7 @@ void ensure_init();
 // live timing: HIP events around launches (enabled by lma_profile_enable)
 // ---------------------------------------------------------------------------
 namespace prof {
-enum Kind { UPDATE = 0, DIAG = 1, TRSM = 2, OTHER = 3 };
+enum Kind { UPDATE = 0, DIAG = 1, TRSM = 2, OTHER = 3, GEMM = 4, CONTRACT = 5 };
 extern bool on;
 struct Rec {
   int kind;
@@ -89,6 +89,19 @@ void timed(int kind, double flops, hipStream_t st, F&& launch, double flops64 = 
 // call after the stream has been synchronised
 void flush();
 }  // namespace prof
+
+// 2 x multiply-adds of tile GEMM outputs [o0, o1) on their valid entries
+template <typename T>
+double gemm_flops(const std::vector<GemmTerm<T>>& terms, const std::vector<GemmOut>& outs, int64_t o0, int64_t o1) {
+  double fl = 0.0;
+  for (int64_t i = o0; i < o1; ++i) {
+    const GemmOut& o = outs[i];
+    double k = 0.0;
+    for (int t = o.t0; t < o.t1; ++t) k += terms[t].k1 - terms[t].k0;
+    fl += 2.0 * o.rows * o.cols * k;
+  }
+  return fl;
+}
 
 // Lock-step column schedule of one engine run, uploaded once.
 template <typename T>

@@ -51,3 +51,11 @@ def test_version_and_error_without_gpu(so):
 def test_binding_struct_matches_header_layout():
     # lma_problem: 5 int64, 6 pointers/doubles in order, then int32 x2 and int64
     assert ctypes.sizeof(lma._Problem) == 5 * 8 + 5 * 8 + 8 + 4 + 4 + 8
+
+
+def test_profile_struct_matches_header_layout():
+    # lma_profile: 6 doubles, 2 int64, 4 doubles, 2 int64
+    assert ctypes.sizeof(lma.Profile) == 14 * 8
+    names = [f for f, _ in lma.Profile._fields_]
+    assert names[:8] == ["update_ms", "diag_ms", "trsm_ms", "other_ms", "update_alg_flops",
+                         "update_alg_flops_f64", "update_launches", "other_launches"]
