@@ -24,6 +24,8 @@ PRECISION = {"fp64": 0, "mixed": 1}
 EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml",
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
            "lma_profile_read", "lma_release_cache")
+DS_EXPORTS = ("lma_ds_create", "lma_ds_free", "lma_ds_set_params", "lma_ds_get_params", "lma_ds_features",
+              "lma_ds_forward", "lma_ds_backward", "lma_ds_adam")
 
 
 class LmaError(RuntimeError):
@@ -94,6 +96,23 @@ def load(path: str = LIB_PATH):
     lib.lma_profile_enable.restype = None
     lib.lma_profile_read.argtypes = [ctypes.POINTER(Profile), ctypes.c_int]
     lib.lma_profile_read.restype = st
+    fp, f32 = ctypes.POINTER(ctypes.c_float), ctypes.c_float
+    lib.lma_ds_create.argtypes = [i64, i64, ctypes.POINTER(vp)]
+    lib.lma_ds_create.restype = st
+    lib.lma_ds_free.argtypes = [vp]
+    lib.lma_ds_free.restype = None
+    lib.lma_ds_set_params.argtypes = [vp, fp]
+    lib.lma_ds_set_params.restype = st
+    lib.lma_ds_get_params.argtypes = [vp, fp]
+    lib.lma_ds_get_params.restype = st
+    lib.lma_ds_features.argtypes = [vp, vp, vp, i64, ctypes.c_int32, vp, vp]
+    lib.lma_ds_features.restype = st
+    lib.lma_ds_forward.argtypes = [vp, i64, ctypes.POINTER(i64), ctypes.POINTER(i64), vp, vp, vp]
+    lib.lma_ds_forward.restype = st
+    lib.lma_ds_backward.argtypes = [vp, vp, vp, vp, ctypes.POINTER(ctypes.c_double), vp]
+    lib.lma_ds_backward.restype = st
+    lib.lma_ds_adam.argtypes = [vp, f32, f32, f32, f32, vp]
+    lib.lma_ds_adam.restype = st
     _lib = lib
     return lib
 

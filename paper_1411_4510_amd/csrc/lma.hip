@@ -106,6 +106,8 @@ void release() {
 }
 }  // namespace devcache
 
+void set_last_error(const std::string& msg) { g_err = msg; }
+
 bool g_inited = false;
 void ensure_init() {
   if (g_inited) return;

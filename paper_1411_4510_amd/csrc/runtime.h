@@ -59,6 +59,8 @@ void release();
 }  // namespace devcache
 
 void ensure_init();
+// message returned by lma_last_error() on this thread
+void set_last_error(const std::string& msg);
 
 // ---------------------------------------------------------------------------
 // live timing: HIP events around launches (enabled by lma_profile_enable)

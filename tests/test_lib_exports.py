@@ -11,8 +11,8 @@ import paper_1411_4510_amd as lma
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    src = open(os.path.join(ROOT, "include", "lma.h")).read()
+def header_functions(name="lma.h"):
+    src = open(os.path.join(ROOT, "include", name)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(lma_[a-z_]+)\s*\(", src)))
 
@@ -22,6 +22,7 @@ def test_header_declares_the_boundary():
     for n in ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_last_error", "lma_failed_block"):
         assert n in names
     assert set(names) == set(lma.EXPORTS)
+    assert set(header_functions("lma_ds.h")) == set(lma.DS_EXPORTS)
 
 
 @pytest.fixture(scope="module")
@@ -32,7 +33,7 @@ def so():
 
 
 def test_library_exports_every_declared_symbol(so):
-    for name in header_functions():
+    for name in header_functions() + header_functions("lma_ds.h"):
         assert hasattr(so, name), name
 
 
