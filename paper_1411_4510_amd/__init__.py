@@ -74,6 +74,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build the HIP library first (paper_1411_4510_amd.build)")
+    # torch ships its own HIP runtime under the same soname; importing it first
+    # makes the library bind to that runtime instead of loading a second one
+    # (two HIP/HSA runtimes in one process cannot both open the device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
     lib.lma_fit.argtypes = [ctypes.POINTER(_Problem), vp, ctypes.POINTER(vp)]

@@ -107,13 +107,18 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
 // diag: Cholesky of the diagonal tile (j, j) in LDS, its log-diagonal, and the
 // inverse of the factor for the triangular solves of the tiles below.
 // ---------------------------------------------------------------------------
+// The tile is factored and inverted in float64 for every storage type (the
+// float32 window factors of the mixed mode included): the diagonal tiles of
+// late column steps hold Schur complements near the noise level, and their
+// factor and inverse feed every later tile.
 template <typename T>
 __global__ __launch_bounds__(NT) void k_diag(StepArgs<T> a, const int32_t* __restrict__ plist) {
+  typedef double TA;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* A = reinterpret_cast<T*>(smem_raw);  // [TB][DIAG_LD]
-  T* col0 = A + TB * DIAG_LD;             // [TB] double-buffered column copies
-  T* col1 = col0 + TB;
-  T* part = col1 + TB;                    // [2][TB] partial dot products
+  TA* A = reinterpret_cast<TA*>(smem_raw);  // [TB][DIAG_LD]
+  TA* col0 = A + TB * DIAG_LD;              // [TB] double-buffered column copies
+  TA* col1 = col0 + TB;
+  TA* part = col1 + TB;                     // [2][TB] partial dot products
   __shared__ int bad;
   __shared__ double lsum[NT / 64];
   const int p = plist[blockIdx.x];
@@ -124,23 +129,23 @@ __global__ __launch_bounds__(NT) void k_diag(StepArgs<T> a, const int32_t* __res
   if (tid == 0) bad = 0;
   for (int idx = tid; idx < TB * TB; idx += NT) {
     const int r = idx >> 7, c = idx & (TB - 1);
-    A[r * DIAG_LD + c] = c <= r ? src[(int64_t)r * rj.ld + c] : T(0);
+    A[r * DIAG_LD + c] = c <= r ? (TA)src[(int64_t)r * rj.ld + c] : TA(0);
   }
   __syncthreads();
   // Right-looking factorisation; the column scaling of step k runs
   // concurrently with the trailing update of step k+1 (disjoint columns).
   const int tr = tid >> 4, tc = tid & 15;
   for (int k = 0; k < TB; ++k) {
-    T dkk = A[k * DIAG_LD + k];
-    const bool ok = dkk > T(0);
-    if (!ok) dkk = T(1);
-    const T rinv = T(1) / dkk;
+    TA dkk = A[k * DIAG_LD + k];
+    const bool ok = dkk > TA(0);
+    if (!ok) dkk = TA(1);
+    const TA rinv = TA(1) / dkk;
     for (int r = k + 1 + tr; r < TB; r += 16) {
-      const T lrk = A[r * DIAG_LD + k] * rinv;
+      const TA lrk = A[r * DIAG_LD + k] * rinv;
       for (int c = k + 1 + tc; c <= r; c += 16) A[r * DIAG_LD + c] -= lrk * A[c * DIAG_LD + k];
     }
     __syncthreads();
-    const T piv = k_sqrt(dkk), ip = T(1) / piv;
+    const TA piv = k_sqrt(dkk), ip = TA(1) / piv;
     for (int r = k + 1 + tid; r < TB; r += NT) A[r * DIAG_LD + k] *= ip;
     if (tid == 0) {
       A[k * DIAG_LD + k] = piv;
@@ -152,7 +157,7 @@ __global__ __launch_bounds__(NT) void k_diag(StepArgs<T> a, const int32_t* __res
   // store L_jj and its log-diagonal
   for (int idx = tid; idx < TB * TB; idx += NT) {
     const int r = idx >> 7, c = idx & (TB - 1);
-    src[(int64_t)r * rj.ld + c] = c <= r ? A[r * DIAG_LD + c] : T(0);
+    src[(int64_t)r * rj.ld + c] = c <= r ? (T)A[r * DIAG_LD + c] : T(0);
   }
   {
     double ls = 0.0;
@@ -169,12 +174,12 @@ __global__ __launch_bounds__(NT) void k_diag(StepArgs<T> a, const int32_t* __res
     a.logdiag[(int64_t)p * a.maxT + a.j] = (a.j >= pd.ld_from) ? tot : 0.0;
   }
   for (int jj = TB - 1; jj >= 0; --jj) {
-    T* cur = ((TB - 1 - jj) & 1) ? col1 : col0;   // old column jj (rows > jj valid)
-    T* nxt = ((TB - 1 - jj) & 1) ? col0 : col1;
-    const T xjj = T(1) / A[jj * DIAG_LD + jj];      // not written before the next barrier
+    TA* cur = ((TB - 1 - jj) & 1) ? col1 : col0;  // old column jj (rows > jj valid)
+    TA* nxt = ((TB - 1 - jj) & 1) ? col0 : col1;
+    const TA xjj = TA(1) / A[jj * DIAG_LD + jj];     // not written before the next barrier
     {
       const int r = jj + 1 + (tid >> 1), h = tid & 1;
-      T s = T(0);
+      TA s = TA(0);
       if (r < TB) {
         for (int k = jj + 1 + h; k <= r; k += 2) s += A[r * DIAG_LD + k] * cur[k];
         part[h * TB + r] = s;
@@ -184,14 +189,14 @@ __global__ __launch_bounds__(NT) void k_diag(StepArgs<T> a, const int32_t* __res
     for (int r = jj + 1 + tid; r < TB; r += NT) A[r * DIAG_LD + jj] = -xjj * (part[r] + part[TB + r]);
     if (tid == 0) A[jj * DIAG_LD + jj] = xjj;
     if (jj > 0)
-      for (int r = tid; r < TB; r += NT) nxt[r] = r >= jj ? A[r * DIAG_LD + (jj - 1)] : T(0);
+      for (int r = tid; r < TB; r += NT) nxt[r] = r >= jj ? A[r * DIAG_LD + (jj - 1)] : TA(0);
     __syncthreads();
   }
   __syncthreads();
   T* inv = a.invdiag + pd.invdiag_off + (int64_t)a.j * TB * TB;
   for (int idx = tid; idx < TB * TB; idx += NT) {
     const int r = idx >> 7, c = idx & (TB - 1);
-    inv[idx] = c <= r ? A[r * DIAG_LD + c] : T(0);
+    inv[idx] = c <= r ? (T)A[r * DIAG_LD + c] : T(0);
   }
 }
 
@@ -299,7 +304,7 @@ void launch_update(const StepArgs<T>& a, bool mixed, hipStream_t st) {
 template <typename T>
 void launch_diag(const StepArgs<T>& a, const int32_t* plist, int np, hipStream_t st) {
   if (np <= 0) return;
-  hipLaunchKernelGGL(k_diag<T>, dim3(np), dim3(NT), diag_lds_bytes<T>(), st, a, plist);
+  hipLaunchKernelGGL(k_diag<T>, dim3(np), dim3(NT), diag_lds_bytes<double>(), st, a, plist);
 }
 
 template <typename T>
@@ -320,7 +325,7 @@ hipError_t engine_init() {
                                      (int)diag_lds_bytes<double>());
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_diag<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)diag_lds_bytes<float>());
+                          (int)diag_lds_bytes<double>());
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_update<double, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(2 * 64 * TB * sizeof(double)));

@@ -21,6 +21,8 @@
 // derivative of the covariance it multiplies; the covariance tiles are
 // regenerated, never stored.  Windows are processed in chunks that fit a
 // device-memory budget.
+#include <cstdlib>
+
 #include "grad.h"
 #include "runtime.h"
 
@@ -117,11 +119,11 @@ int64_t vec_bytes(const std::vector<T>& v) {
 // touch, against the two device blocks they may live in (the fitted state and
 // the gradient workspace).  Throws before anything is launched.
 struct Regions {
-  const char* lo[2];
-  const char* hi[2];
+  const char* lo[3];
+  const char* hi[3];
   void need(const void* p, int64_t bytes, const char* what) const {
     const char* c = reinterpret_cast<const char*>(p);
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 3; ++i)
       if (c >= lo[i] && bytes >= 0 && c + bytes <= hi[i]) return;
     throw Err{LMA_E_ARG, std::string("internal error: gradient operand out of range (") + what + ")"};
   }
@@ -149,15 +151,16 @@ struct GemmBatch {
 };
 
 template <typename TW>
-void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st) {
+void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, TW* win_override = nullptr,
+              TW* inv_override = nullptr, int64_t override_bytes = 0) {
   const int64_t d = f.d, s = f.s, sp = f.sp, M = f.M;
   const int Ts = (int)f.Ts;
   const int64_t Mp = align_up(M, TB);
   const int64_t sp2 = sp * sp;
   const int ncomp = (int)d + 2;
   const bool mixed = f.mixed();
-  TW* winbase = reinterpret_cast<TW*>(f.ptr<char>(f.o_win));
-  TW* wininv = reinterpret_cast<TW*>(f.ptr<char>(f.o_win_inv));
+  TW* winbase = win_override ? win_override : reinterpret_cast<TW*>(f.ptr<char>(f.o_win));
+  TW* wininv = inv_override ? inv_override : reinterpret_cast<TW*>(f.ptr<char>(f.o_win_inv));
   const TW* cvec = mixed ? reinterpret_cast<const TW*>(f.ptr<float>(f.o_c32))
                          : reinterpret_cast<const TW*>(f.ptr<double>(f.o_c64));
   const double* Xs = f.ptr<double>(f.o_Xs64);
@@ -589,6 +592,11 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st) {
     rg.hi[0] = f.ar.base + f.ar.cap;
     rg.lo[1] = reinterpret_cast<const char*>(mem);
     rg.hi[1] = reinterpret_cast<const char*>(mem) + ar.cap;
+    rg.lo[2] = rg.hi[2] = nullptr;
+    if (win_override) {
+      rg.lo[2] = reinterpret_cast<const char*>(win_override);
+      rg.hi[2] = rg.lo[2] + override_bytes;
+    }
     for (const GemmTerm<TW>& t : tw_terms) rg.gterm(t, "window product term");
     for (const GemmTerm<double>& t : d_terms) rg.gterm(t, "float64 product term");
     for (const GemmTerm<TW>& t : x_terms) rg.gterm(t, "inverse-factor term");
@@ -723,6 +731,23 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st) {
   });
   gemm_d(finB);
   contract(it_beg[nchunk], it_beg[nchunk + 1]);
+  if (std::getenv("LMA_GRAD_PARTS")) {  // diagnostic: sums of the partials by term kind
+    std::vector<double> hp((size_t)nitems * ncomp);
+    HIPCHK(hipMemcpyAsync(hp.data(), part, 8 * hp.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<double> sw(ncomp, 0.0), sx(ncomp, 0.0), ss(ncomp, 0.0);
+    for (int64_t i = 0; i < nitems; ++i) {
+      std::vector<double>& dst = i >= it_beg[nchunk] ? ss : (items[i].kind == DC_CROSS ? sx : sw);
+      for (int q = 0; q < ncomp; ++q) dst[q] += hp[(size_t)i * ncomp + q];
+    }
+    const char* nm[3] = {"windows", "cross", "support"};
+    std::vector<double>* v[3] = {&sw, &sx, &ss};
+    for (int k = 0; k < 3; ++k) {
+      std::fprintf(stderr, "grad part %s:", nm[k]);
+      for (int q = 0; q < ncomp; ++q) std::fprintf(stderr, " %.12e", (*v[k])[q]);
+      std::fprintf(stderr, "\n");
+    }
+  }
   prof::timed(prof::OTHER, 0.0, st, [&] { launch_reduce_partials(part, nitems, ncomp, at<double>(ar, o_gdev), st); });
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(grad_host, at<double>(ar, o_gdev), 8 * ncomp, hipMemcpyDeviceToHost, st));
@@ -736,10 +761,33 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st) {
 
 void grad_impl(lma_state& f, double* grad, int64_t budget, hipStream_t st) {
   if (budget <= 0) budget = (int64_t)16 << 30;
-  if (f.mixed())
+  if (f.mixed()) {
     grad_run<float>(f, grad, budget, st);
-  else
+  } else if (std::getenv("LMA_GRAD_F32_FROM_F64")) {
+    // diagnostic: the float32 gradient pass on float32 roundings of the float64
+    // factors (separates the float32 pass's error from the float32 factors')
+    int64_t we = 0, ie = 0;
+    for (int64_t m = 0; m < f.M; ++m) {
+      we += panel_elems(f.Tm[m], (int)f.Ts + 1);
+      ie += (int64_t)f.Tm[m] * TB * TB;
+    }
+    float* buf = nullptr;
+    HIPCHK(hipMalloc(&buf, 4 * (we + ie)));
+    launch_cast(f.ptr<double>(f.o_win), buf, we, st);
+    launch_cast(f.ptr<double>(f.o_win_inv), buf + we, ie, st);
+    HIPCHK(hipGetLastError());
+    try {
+      grad_run<float>(f, grad, budget, st, buf, buf + we, 4 * (we + ie));
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(buf);
+      throw;
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(buf));
+  } else {
     grad_run<double>(f, grad, budget, st);
+  }
 }
 
 }  // namespace lmart
