@@ -172,6 +172,9 @@ def cmd_train(a):
     best, best_params, step = np.inf, None, 0
     hist = []
     for ep in range(a.epochs):
+        if time.time() - t0 > a.time_limit:
+            log(f"time limit reached after {ep} epochs")
+            break
         order = rng.permutation(tr)
         tl = 0.0
         for s in range(steps_per_epoch):
@@ -199,27 +202,6 @@ def cmd_train(a):
 # ---------------------------------------------------------------------------
 # warm start and evaluation
 # ---------------------------------------------------------------------------
-class WarmStart:
-    """Predicts starting log-hyperparameters for a dataset (standardised outputs)."""
-
-    def __init__(self, params, max_rows=65536):
-        from .warmstart import Network
-        self.net = Network(max_rows=max_rows, max_sets=1)
-        self.net.set_params(np.load(params) if isinstance(params, str) else params)
-        self.max_rows = max_rows
-
-    def predict(self, X, y):
-        import torch
-        n, d = X.shape
-        rows = (n + 127) // 128 * 128
-        if rows > self.max_rows:
-            raise ValueError("dataset larger than the network workspace")
-        feats = torch.zeros((rows, 17), dtype=torch.float32, device="cuda")
-        self.net.features(X, y, out=feats[:n])
-        out = self.net.forward(feats, [0, rows], [n]).cpu().numpy()[0]
-        return np.r_[out[:d], out[8], out[9]].astype(np.float64)
-
-
 def steps_to(hist, target, rtol=1e-3):
     for k, v in enumerate(hist):
         if abs(v - target) <= rtol * abs(target):
@@ -228,6 +210,7 @@ def steps_to(hist, target, rtol=1e-3):
 
 
 def evaluate_set(i, ws, steps=150, lr=0.05):
+    """Adam from the default start and from the warm start on held-out set i."""
     import synth
     from synth import gpsets
     from . import LmaError, LmlProblem
@@ -270,6 +253,7 @@ def summarise(rows, cap):
 
 
 def cmd_evaluate(a):
+    from .warmstart import WarmStart
     ws = WarmStart(a.params)
     rows = []
     t0 = time.time()
@@ -305,6 +289,7 @@ def main(argv=None):
     p2.add_argument("--val", type=int, default=1000)
     p2.add_argument("--seed", type=int, default=0)
     p2.add_argument("--workers", type=int, default=12)
+    p2.add_argument("--time-limit", type=float, default=1e9, help="stop starting epochs after this many seconds")
     p3 = sub.add_parser("evaluate")
     p3.add_argument("--params", required=True)
     p3.add_argument("--first", type=int, default=0)

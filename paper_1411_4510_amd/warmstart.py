@@ -7,11 +7,13 @@ marshals arguments (torch tensors provide device memory and streams).
 from __future__ import annotations
 
 import ctypes
+import os
 
 import numpy as np
 
 from . import _check, _stream, load
 
+PARAMS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_params.npy")
 NPARAM = 138762
 NFEAT = 17
 NOUT = 10
@@ -162,3 +164,30 @@ def to_label(log_hyp, d: int, y) -> np.ndarray:
     lab[DMAX] = lh[d] - lv
     lab[DMAX + 1] = lh[d + 1] - lv
     return lab
+
+
+class WarmStart:
+    """Starting log-hyperparameters for LMA fitting, predicted by the trained
+    network (parameters from train_warmstart, shipped beside this module).
+
+    predict(X, y) expects standardised outputs (zero mean, unit variance) and
+    inputs in the unit cube; returns [log l_1..log l_d, log sigma_s^2,
+    log sigma_n^2]."""
+
+    def __init__(self, params=None, max_rows=65536):
+        self.net = Network(max_rows=max_rows, max_sets=1)
+        self.net.set_params(np.load(params or PARAMS_PATH) if params is None or isinstance(params, str) else params)
+        self.max_rows = max_rows
+
+    def predict(self, X, y):
+        import torch
+        n, d = X.shape
+        if d > DMAX:
+            raise ValueError("the warm-start network covers d <= 8")
+        rows = (n + 127) // 128 * 128
+        if rows > self.max_rows:
+            raise ValueError("dataset larger than the network workspace")
+        feats = torch.zeros((rows, NFEAT), dtype=torch.float32, device="cuda")
+        self.net.features(X, y, out=feats[:n])
+        out = self.net.forward(feats, [0, rows], [n]).cpu().numpy()[0]
+        return np.r_[out[:d], out[DMAX], out[DMAX + 1]].astype(np.float64)
