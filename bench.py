@@ -76,7 +76,7 @@ def measured_traffic(kernel_mode):
     with open(path) as f:
         rec = json.load(f)
     h = hashlib.sha256()
-    for fn in ("engine.hip", "engine.h"):
+    for fn in ("engine.hip", "engine.h", "mfma_core.h"):
         with open(os.path.join(ROOT, "paper_1411_4510_amd", "csrc", fn), "rb") as f:
             h.update(f.read())
     if h.hexdigest()[:16] != rec["source_sha256_16"]:
