@@ -115,6 +115,7 @@ void ensure_init() {
   HIPCHK(misc_init());
   HIPCHK(vecsolve_init());
   HIPCHK(grad_init());
+  HIPCHK(kvec_init());
   g_inited = true;
 }
 
@@ -389,10 +390,53 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       f.runD.rt.push_back(r);
     }
     f.runD.schedule();
+    // kernel-times-vector items of the mixed refinement: c' = c - K_DS g over training
+    // tiles, and r_X = c'_X - R_X beta_X over the tiles of every window
+    f.kvcols.clear();
+    f.kvcg.clear();
+    f.kvkmv.clear();
+    if (mixed) {
+      const double* Xs = f.ptr<double>(f.o_Xs64);
+      const double* Ss = f.ptr<double>(f.o_Ss64);
+      kv_support_cols(f.kvcols, Ss, s, d, f.ptr<double>(f.o_g));
+      const int ncs = (int)f.kvcols.size();
+      for (int64_t r0 = 0; r0 < n; r0 += TB) {
+        KvItem it = kv_item(Xs + r0 * d, (int)std::min<int64_t>(TB, n - r0), 0, ncs);
+        it.base0 = f.ptr<double>(f.o_c64) + r0;
+        it.out0 = f.ptr<double>(f.o_cg) + r0;
+        f.kvcg.push_back(it);
+      }
+      int64_t vo = 0;
+      for (int64_t m = 0; m < M; ++m) {
+        const WinGeom g = win_geom(f.bp, M, f.B, m);
+        const int c0 = (int)f.kvcols.size();
+        kv_window_cols(f.kvcols, g, Xs, d, f.ptr<double>(f.o_xJ) + vo, f.ptr<double>(f.o_xW) + vo);
+        const int c1 = (int)f.kvcols.size();
+        for (int i = 0; i < g.T; ++i) {
+          int nv;
+          const int64_t pt = win_tile_point(g, i, &nv);
+          KvItem it = kv_item(Xs + pt * d, nv, c0, c1);
+          it.base0 = f.ptr<double>(f.o_cg) + pt;
+          it.vt = f.ptr<double>(f.o_Vt64) + pt * sp;
+          it.h0 = f.ptr<double>(f.o_hJ) + m * sp;
+          it.h1 = f.ptr<double>(f.o_hW) + m * sp;
+          it.self0 = f.ptr<double>(f.o_xJ) + vo + (int64_t)i * TB;
+          it.self1 = f.ptr<double>(f.o_xW) + vo + (int64_t)i * TB;
+          it.out0 = f.ptr<double>(f.o_tJ) + vo + (int64_t)i * TB;
+          it.out1 = f.ptr<double>(f.o_tW) + vo + (int64_t)i * TB;
+          it.flag = i < g.tw ? 1 : 0;
+          f.kvkmv.push_back(it);
+        }
+        vo += (int64_t)g.T * TB;
+      }
+    }
   };
   build_runs(nullptr);
   const int64_t meta = f.runS.meta_bytes() + (mixed ? f.runW32.meta_bytes() : f.runW64.meta_bytes()) +
                        f.runD.meta_bytes();
+  f.o_kvcols = ar.reserve(sizeof(KvCol) * std::max<size_t>(f.kvcols.size(), 1));
+  f.o_kvcg = ar.reserve(sizeof(KvItem) * std::max<size_t>(f.kvcg.size(), 1));
+  f.o_kvkmv = ar.reserve(sizeof(KvItem) * std::max<size_t>(f.kvkmv.size(), 1));
   const int64_t sterm_bytes = mixed ? sizeof(GemmTerm<float>) * f.sum32.size() : sizeof(GemmTerm<double>) * f.sum64.size();
   f.o_meta = ar.reserve(meta);
   f.o_sumterms = ar.reserve(sterm_bytes);
@@ -433,6 +477,15 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_sumterms), f.sum64.data(), sterm_bytes, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_sumout), f.sumout.data(), sizeof(GemmOut) * f.sumout.size(),
                           hipMemcpyHostToDevice, st));
+    if (!f.kvcols.empty())
+      HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_kvcols), f.kvcols.data(), sizeof(KvCol) * f.kvcols.size(),
+                            hipMemcpyHostToDevice, st));
+    if (!f.kvcg.empty())
+      HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_kvcg), f.kvcg.data(), sizeof(KvItem) * f.kvcg.size(),
+                            hipMemcpyHostToDevice, st));
+    if (!f.kvkmv.empty())
+      HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_kvkmv), f.kvkmv.data(), sizeof(KvItem) * f.kvkmv.size(),
+                            hipMemcpyHostToDevice, st));
   }
   // ---- compute
   int32_t* status = f.ptr<int32_t>(f.o_status);
@@ -599,7 +652,7 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     auto full_solve = [&](auto* panels, auto* invs, double* vJ, double* vW) {
       auto va = winvec(panels, invs, vJ, vW);
       using TT = typename std::remove_const<typename std::remove_pointer<decltype(panels)>::type>::type;
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_fwd<TT>(va, (int)M, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_fwd<TT>(va, (int)M, maxTw, st); });
       prof::timed(prof::OTHER, 0.0, st, [&] { launch_bwd<TT>(va, (int)M, st); });
       HIPCHK(hipGetLastError());
     };
@@ -617,33 +670,21 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       beta_solve(P, I);
       prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
       // 2. one refinement of beta against the float64 residual covariance
-      CgArgs ca;
-      ca.n = n;
-      ca.d = (int)d;
-      ca.s = (int)s;
-      ca.Xs = f.ptr<double>(f.o_Xs64);
-      ca.Ss = f.ptr<double>(f.o_Ss64);
-      ca.c = f.ptr<double>(f.o_c64);
-      ca.g = g;
-      ca.sf2 = f.sf2;
-      ca.out = cg;
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_cg(ca, st); });
-      KmvArgs ka;
-      ka.w = f.wt;
-      ka.Xs = f.ptr<double>(f.o_Xs64);
-      ka.Vt = f.ptr<double>(f.o_Vt64);
-      ka.rhs_pt = cg;
-      ka.xJ = xJ;
-      ka.xW = xW;
-      ka.hJ = ha.hJ;
-      ka.hW = ha.hW;
-      ka.rJ = tJ;
-      ka.rW = tW;
-      ka.d = (int)d;
-      ka.sp = (int)sp;
-      ka.sf2 = f.sf2;
-      ka.sn2 = f.sn2;
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_kmv(ka, (int)M, maxTw, st); });
+      KvArgs kv;
+      kv.cols = reinterpret_cast<const KvCol*>(f.ptr<char>(f.o_kvcols));
+      kv.d = (int)d;
+      kv.sp = (int)sp;
+      kv.sf2 = f.sf2;
+      kv.sn2 = f.sn2;
+      kv.mu = 0.0;
+      kv.items = reinterpret_cast<const KvItem*>(f.ptr<char>(f.o_kvcg));
+      kv.nitems = (int32_t)f.kvcg.size();
+      kv.mode = KV_CG;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_kvec(kv, st); });
+      kv.items = reinterpret_cast<const KvItem*>(f.ptr<char>(f.o_kvkmv));
+      kv.nitems = (int32_t)f.kvkmv.size();
+      kv.mode = KV_KMV;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_kvec(kv, st); });
       full_solve(P, I, tJ, tW);
       prof::timed(prof::OTHER, 0.0, st, [&] { launch_axpy2(xJ, xW, tJ, tW, 1.0, f.vec_elems, st); });
       prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
@@ -801,6 +842,9 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   Run<double> runD;
   std::vector<GemmTerm<TW>> terms;
   std::vector<GemmOut> outs;
+  std::vector<KvCol> kvcols;
+  std::vector<KvItem> kvitems;
+  const int64_t o_hq = ar.reserve(8 * M * sp);
   auto build = [&](char* base) {
     ar.base = base;
     runS = Run<double>();
@@ -808,6 +852,8 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     runD = Run<double>();
     terms.clear();
     outs.clear();
+    kvcols.clear();
+    kvitems.clear();
     // S run in solve-only mode: right-hand sides are the test rows -> V_U^T
     const int Rn = (int)cdiv(n_u, TB);
     runS.add_problem(Ts, Rn, 0, true, -1);
@@ -819,6 +865,30 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
                                           0));
     }
     runS.schedule();
+    // predictive mean: per test tile of block q, the support tiles with g, the J_m tiles
+    // of windows m = q-B..q with beta_J and (m < q) the W_m tiles with beta_W
+    {
+      const double* Xs64 = f.ptr<double>(f.o_Xs64);
+      for (int64_t q = 0; q < M; ++q) {
+        if (ubp[q + 1] == ubp[q]) continue;
+        const int c0 = (int)kvcols.size();
+        kv_support_cols(kvcols, f.ptr<double>(f.o_Ss64), f.s, d, f.ptr<double>(f.o_g));
+        for (int64_t dl = 0; dl <= f.B && dl <= q; ++dl) {
+          const int64_t m = q - dl;
+          const int64_t vo = f.wt_host[6 * M + m];
+          kv_window_cols(kvcols, win_geom(f.bp, M, f.B, m), Xs64, d, f.ptr<double>(f.o_xJ) + vo,
+                         dl > 0 ? f.ptr<double>(f.o_xW) + vo : nullptr);
+        }
+        const int c1 = (int)kvcols.size();
+        for (int64_t u0 = ubp[q]; u0 < ubp[q + 1]; u0 += TB) {
+          KvItem it = kv_item(at<double>(ar, o_Us64) + u0 * d, (int)std::min<int64_t>(TB, ubp[q + 1] - u0), c0, c1);
+          it.vt = at<double>(ar, o_VtU64) + u0 * sp;
+          it.h0 = at<double>(ar, o_hq) + q * sp;
+          it.out0 = mean + u0;
+          kvitems.push_back(it);
+        }
+      }
+    }
     // window runs in solve-only mode
     const double* Us = at<double>(ar, o_Us64);
     const double* VtU = at<double>(ar, o_VtU64);
@@ -906,6 +976,8 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     dl_split[f.B + 1] = idx;
   }
   const int64_t o_meta = ar.reserve(runS.meta_bytes() + runW.meta_bytes() + runD.meta_bytes());
+  const int64_t o_kvc = ar.reserve(sizeof(KvCol) * std::max<size_t>(kvcols.size(), 1));
+  const int64_t o_kvi = ar.reserve(sizeof(KvItem) * std::max<size_t>(kvitems.size(), 1));
   const int64_t o_terms = ar.reserve(sizeof(GemmTerm<TW>) * std::max<size_t>(terms.size(), 1));
   const int64_t o_outs = ar.reserve(sizeof(GemmOut) * std::max<size_t>(outs.size(), 1));
   ar.cap = ar.used;
@@ -936,6 +1008,12 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     if (!outs.empty())
       HIPCHK(hipMemcpyAsync(at<char>(ar, o_outs), outs.data(), sizeof(GemmOut) * outs.size(), hipMemcpyHostToDevice,
                             st));
+    if (!kvcols.empty())
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_kvc), kvcols.data(), sizeof(KvCol) * kvcols.size(), hipMemcpyHostToDevice,
+                            st));
+    if (!kvitems.empty())
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_kvi), kvitems.data(), sizeof(KvItem) * kvitems.size(),
+                            hipMemcpyHostToDevice, st));
   }
   std::vector<int32_t> ublk(n_u);
   for (int64_t q = 0; q < M; ++q)
@@ -982,27 +1060,20 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   };
   exec(runS, f.ptr<double>(f.o_Lss_inv), 0);
   {
-    MeanArgs ma;
-    ma.w = f.wt;
-    ma.n_u = n_u;
-    ma.B = (int)f.B;
-    ma.d = (int)d;
-    ma.s = (int)f.s;
-    ma.sp = (int)sp;
-    ma.ublk = at<int32_t>(ar, o_ublk);
-    ma.Us = at<double>(ar, o_Us64);
-    ma.Ss = f.ptr<double>(f.o_Ss64);
-    ma.Xs = f.ptr<double>(f.o_Xs64);
-    ma.VtU = at<double>(ar, o_VtU64);
-    ma.g = f.ptr<double>(f.o_g);
-    ma.xJ = f.ptr<double>(f.o_xJ);
-    ma.xW = f.ptr<double>(f.o_xW);
-    ma.hJ = f.ptr<double>(f.o_hJ);
-    ma.hW = f.ptr<double>(f.o_hW);
-    ma.mu = f.mu;
-    ma.sf2 = f.sf2;
-    ma.mean = mean;
-    prof::timed(prof::OTHER, 0.0, st, [&] { launch_mean(ma, st); });
+    prof::timed(prof::OTHER, 0.0, st, [&] {
+      launch_hq(f.ptr<double>(f.o_hJ), f.ptr<double>(f.o_hW), at<double>(ar, o_hq), (int)M, (int)f.B, (int)sp, st);
+    });
+    KvArgs kv;
+    kv.items = at<KvItem>(ar, o_kvi);
+    kv.cols = at<KvCol>(ar, o_kvc);
+    kv.nitems = (int32_t)kvitems.size();
+    kv.mode = KV_MEAN;
+    kv.d = (int)d;
+    kv.sp = (int)sp;
+    kv.sf2 = f.sf2;
+    kv.sn2 = f.sn2;
+    kv.mu = f.mu;
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_kvec(kv, st); });
     HIPCHK(hipGetLastError());
   }
   if (!var) {

@@ -80,7 +80,7 @@ hipError_t engine_init();
 
 namespace lma {
 
-// Per-window geometry used by the vector solves and the mean kernel.
+// Per-window geometry used by the vector solves.
 struct WinTab {
   const int64_t* wstart;   // first training row of W_m
   const int64_t* wlen;     // |W_m|
@@ -107,22 +107,6 @@ struct WinVecArgs {
   double* vW;
 };
 
-// r = c' - R_X x in float64 (R_X x = K_XX x + sigma_n^2 x - V_X^T h, h = V_X x),
-// for X = J_m and X = W_m.
-struct KmvArgs {
-  WinTab w;
-  const double* Xs;        // scaled training inputs [n][d]
-  const double* Vt;        // [n][sp]
-  const double* rhs_pt;    // c' per training point
-  const double* xJ;
-  const double* xW;
-  const double* hJ;        // [M][sp]
-  const double* hW;
-  double* rJ;
-  double* rW;
-  int d, sp;
-  double sf2, sn2;
-};
 
 // Global correction of g (mixed precision): H = sum_m (hJ_m - hW_m),
 // rho = L_SS (H - L_SS^T g)  (= y_ddot - Sigma_ddot g with exact window solves).
@@ -146,45 +130,14 @@ struct HArgs {
   int sp, M;
 };
 
-// c' = c - K_DS g per training point.
-struct CgArgs {
-  int64_t n;
-  int d, s;
-  const double* Xs;
-  const double* Ss;
-  const double* c;
-  const double* g;
-  double sf2;
-  double* out;
-};
 
-// mean_u = mu + k_u^T g + sum_{m=q-B..q} (K_{u,J_m} xJ_m - V_u . hJ_m)
-//                      - sum_{m=q-B..q-1} (K_{u,W_m} xW_m - V_u . hW_m)
-struct MeanArgs {
-  WinTab w;
-  int64_t n_u;
-  int B, d, s, sp;
-  const int32_t* ublk;
-  const double* Us;
-  const double* Ss;
-  const double* Xs;
-  const double* VtU;
-  const double* g;
-  const double* xJ;
-  const double* xW;
-  const double* hJ;
-  const double* hW;
-  double mu, sf2;
-  double* mean;
-};
 
 template <typename TW>
 void launch_ycp(const WinVecArgs<TW>& a, int M, int maxT, hipStream_t st);
 template <typename TW>
-void launch_fwd(const WinVecArgs<TW>& a, int M, hipStream_t st);
+void launch_fwd(const WinVecArgs<TW>& a, int M, int maxT, hipStream_t st);
 template <typename TW>
 void launch_bwd(const WinVecArgs<TW>& a, int M, hipStream_t st);
-void launch_kmv(const KmvArgs& a, int M, int maxT, hipStream_t st);
 void launch_gres(const GresArgs& a, hipStream_t st);
 // g += dg and t = L_SS^T dg (one workgroup)
 void launch_gupdate(const double* L, const double* dg, double* g, double* t, int sp, hipStream_t st);
@@ -196,7 +149,5 @@ void launch_gather(const WinTab& w, const double* pt, double* vJ, double* vW, in
 void launch_axpy2(double* vJ, double* vW, const double* xJ, const double* xW, double alpha, int64_t nvec,
                   hipStream_t st);
 void launch_h(const HArgs& a, hipStream_t st);
-void launch_cg(const CgArgs& a, hipStream_t st);
-void launch_mean(const MeanArgs& a, hipStream_t st);
 
 }  // namespace lma

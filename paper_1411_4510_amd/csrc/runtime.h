@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "engine.h"
+#include "kvec.h"
 #include "lma.h"
 #include "misc.h"
 
@@ -270,6 +271,10 @@ struct lma_state {
   std::vector<lma::GemmOut> sumout;
   std::vector<int64_t> wt_host;
   int64_t o_sumterms = -1, o_sumout = -1;
+  // kernel-times-vector items of the mixed-precision refinement (c' and window residuals)
+  std::vector<lma::KvCol> kvcols;
+  std::vector<lma::KvItem> kvcg, kvkmv;
+  int64_t o_kvcols = -1, o_kvcg = -1, o_kvkmv = -1;
   // results
   std::vector<double> g, ydd;
   double qsum = 0, ld_R = 0, ld_ss = 0, ld_dd = 0, ydg = 0, lml = 0;
@@ -330,6 +335,55 @@ inline WinGeom win_geom(const std::vector<int64_t>& bp, int64_t M, int64_t B, in
   g.tb = (int)cdiv(g.b, TB);
   g.T = g.tw + g.tb;
   return g;
+}
+
+// First training row and valid rows of J row tile i of a window.
+inline int64_t win_tile_point(const WinGeom& g, int i, int* nv) {
+  if (i < g.tw) {
+    *nv = (int)std::min<int64_t>(TB, g.w - (int64_t)i * TB);
+    return g.wstart + (int64_t)i * TB;
+  }
+  *nv = (int)std::min<int64_t>(TB, g.b - (int64_t)(i - g.tw) * TB);
+  return g.dstart + (int64_t)(i - g.tw) * TB;
+}
+
+// Column tiles of window m for a kernel-times-vector item: v0 over J_m, v1 over
+// W_m (or none).
+inline void kv_window_cols(std::vector<KvCol>& cols, const WinGeom& g, const double* Xs, int64_t d, const double* v0,
+                           const double* v1) {
+  for (int j = 0; j < g.T; ++j) {
+    int nv;
+    const int64_t p = win_tile_point(g, j, &nv);
+    KvCol c;
+    c.x = Xs + p * d;
+    c.v0 = v0 ? v0 + (int64_t)j * TB : nullptr;
+    c.v1 = (v1 && j < g.tw) ? v1 + (int64_t)j * TB : nullptr;
+    c.nc = nv;
+    c.pad_ = 0;
+    cols.push_back(c);
+  }
+}
+
+inline void kv_support_cols(std::vector<KvCol>& cols, const double* Ss, int64_t s, int64_t d, const double* g) {
+  for (int64_t t = 0; t * TB < s; ++t) {
+    KvCol c;
+    c.x = Ss + t * TB * d;
+    c.v0 = g + t * TB;
+    c.v1 = nullptr;
+    c.nc = (int)std::min<int64_t>(TB, s - t * TB);
+    c.pad_ = 0;
+    cols.push_back(c);
+  }
+}
+
+inline KvItem kv_item(const double* x, int nr, int c0, int c1) {
+  KvItem it;
+  std::memset(&it, 0, sizeof it);
+  it.x = x;
+  it.nr = nr;
+  it.c0 = c0;
+  it.c1 = c1;
+  return it;
 }
 
 // J row tiles of window m (descriptors shared by fit and predict runs).

@@ -46,81 +46,120 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// triangular solves of one vector per window (one workgroup per window)
+// triangular solves of one vector per window (one workgroup of 8 waves per
+// window; the panels are streamed once per solve with 16-byte loads)
 // ---------------------------------------------------------------------------
+constexpr int SOLVE_NT = 512;
+constexpr size_t FWD_LDS_MAX = 150 * 1024;  // solved prefix of windows up to 19200 rows in LDS
 
-// forward, left-looking: t_i = v_i - L_{i,<i} v_{<i}, v_i = L_ii^-1 t_i.
-// One wave per row for the panel dot (lanes along k, coalesced).
 template <typename TW>
-__device__ void fwd_solve(const TW* base, const TW* inv, double* v, int nt, double* t) {
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+  static constexpr int n = 2;
+};
+
+// forward, left-looking: t_i = v_i - L_{i,<i} x_{<i}, x_i = L_ii^-1 t_i, x in v.
+// xs holds the solved prefix (LDS when it fits, else v itself).
+template <typename TW>
+__device__ void fwd_solve(const TW* base, const TW* inv, double* v, int nt, double* xs, double* t) {
+  typedef typename Vec16<TW>::type VT;
+  constexpr int NV = Vec16<TW>::n, STEP = 64 * NV;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   for (int i = 0; i < nt; ++i) {
     const TW* P = base + jp_off(i);
     const int64_t ld = (int64_t)(i + 1) * TB;
     const int K = i * TB;
-    for (int q = 0; q < TB / 4; ++q) {
-      const int r = wv + 4 * q;
+    for (int r = wv; r < TB; r += SOLVE_NT / 64) {
       const TW* row = P + (int64_t)r * ld;
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int k = lane;
-      for (; k + 192 < K; k += 256) {
-        s0 += (double)row[k] * v[k];
-        s1 += (double)row[k + 64] * v[k + 64];
-        s2 += (double)row[k + 128] * v[k + 128];
-        s3 += (double)row[k + 192] * v[k + 192];
+      int k = lane * NV;
+      for (; k + 3 * STEP < K; k += 4 * STEP) {
+        const VT a0 = *(const VT*)(row + k), a1 = *(const VT*)(row + k + STEP);
+        const VT a2 = *(const VT*)(row + k + 2 * STEP), a3 = *(const VT*)(row + k + 3 * STEP);
+#pragma unroll
+        for (int e = 0; e < NV; ++e) {
+          s0 += (double)a0[e] * xs[k + e];
+          s1 += (double)a1[e] * xs[k + STEP + e];
+          s2 += (double)a2[e] * xs[k + 2 * STEP + e];
+          s3 += (double)a3[e] * xs[k + 3 * STEP + e];
+        }
       }
-      for (; k < K; k += 64) s0 += (double)row[k] * v[k];
+      for (; k < K; k += STEP) {
+        const VT a0 = *(const VT*)(row + k);
+#pragma unroll
+        for (int e = 0; e < NV; ++e) s0 += (double)a0[e] * xs[k + e];
+      }
       const double s = wave_sum((s0 + s1) + (s2 + s3));
       if (lane == 0) t[r] = v[K + r] - s;
     }
     __syncthreads();
     const TW* Li = inv + (int64_t)i * TB * TB;
-    for (int q = 0; q < TB / 4; ++q) {
-      const int r = wv + 4 * q;
+    for (int r = wv; r < TB; r += SOLVE_NT / 64) {
       double s = 0.0;
       for (int c = lane; c <= r; c += 64) s += (double)Li[(int64_t)r * TB + c] * t[c];
       s = wave_sum(s);
-      if (lane == 0) v[K + r] = s;
+      if (lane == 0) {
+        v[K + r] = s;
+        xs[K + r] = s;
+      }
     }
     __syncthreads();
   }
 }
 
 // backward, right-looking: x_i = L_ii^-T v_i, then v_{<i} -= L_{i,<i}^T x_i
-// (row panel i, one thread per column, coalesced along the row).
+// (row panel i; each thread owns NV consecutive columns, rows streamed in order).
 template <typename TW>
 __device__ void bwd_solve(const TW* base, const TW* inv, double* v, int nt, double* xi, double* t) {
+  typedef typename Vec16<TW>::type VT;
+  constexpr int NV = Vec16<TW>::n;
   const int tid = threadIdx.x;
   for (int i = nt - 1; i >= 0; --i) {
     if (tid < TB) t[tid] = v[i * TB + tid];
     __syncthreads();
     if (tid < TB) {
       const TW* Li = inv + (int64_t)i * TB * TB;
-      double s = 0.0;
-      for (int c = tid; c < TB; ++c) s += (double)Li[(int64_t)c * TB + tid] * t[c];
-      xi[tid] = s;
-      v[i * TB + tid] = s;
+      double s0 = 0.0, s1 = 0.0;
+      int c = tid;
+      for (; c + 1 < TB; c += 2) {
+        s0 += (double)Li[(int64_t)c * TB + tid] * t[c];
+        s1 += (double)Li[(int64_t)(c + 1) * TB + tid] * t[c + 1];
+      }
+      for (; c < TB; ++c) s0 += (double)Li[(int64_t)c * TB + tid] * t[c];
+      xi[tid] = s0 + s1;
+      v[i * TB + tid] = s0 + s1;
     }
     __syncthreads();
     const TW* P = base + jp_off(i);
     const int64_t ld = (int64_t)(i + 1) * TB;
-    for (int col = tid; col < i * TB; col += blockDim.x) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int col = tid * NV; col < i * TB; col += SOLVE_NT * NV) {
+      double acc[NV];
+#pragma unroll
+      for (int e = 0; e < NV; ++e) acc[e] = 0.0;
 #pragma unroll 4
-      for (int r = 0; r < TB; r += 4) {
-        s0 += (double)P[(int64_t)r * ld + col] * xi[r];
-        s1 += (double)P[(int64_t)(r + 1) * ld + col] * xi[r + 1];
-        s2 += (double)P[(int64_t)(r + 2) * ld + col] * xi[r + 2];
-        s3 += (double)P[(int64_t)(r + 3) * ld + col] * xi[r + 3];
+      for (int r = 0; r < TB; ++r) {
+        const VT a = *(const VT*)(P + (int64_t)r * ld + col);
+        const double x = xi[r];
+#pragma unroll
+        for (int e = 0; e < NV; ++e) acc[e] += (double)a[e] * x;
       }
-      v[col] -= (s0 + s1) + (s2 + s3);
+#pragma unroll
+      for (int e = 0; e < NV; ++e) v[col + e] -= acc[e];
     }
     __syncthreads();
   }
 }
 
-template <typename TW>
-__global__ __launch_bounds__(256) void k_fwd(WinVecArgs<TW> a) {
+template <typename TW, bool XS_LDS>
+__global__ __launch_bounds__(SOLVE_NT) void k_fwd(WinVecArgs<TW> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ double t[TB];
   const int m = blockIdx.x;
   const WinTab& w = a.w;
@@ -128,12 +167,16 @@ __global__ __launch_bounds__(256) void k_fwd(WinVecArgs<TW> a) {
   const int64_t vo = w.vec[m];
   const TW* base = a.panels + w.panel[m];
   const TW* inv = a.invs + w.inv[m];
-  fwd_solve<TW>(base, inv, a.vJ + vo, T, t);
-  if (tw > 0) fwd_solve<TW>(base, inv, a.vW + vo, tw, t);
+  double* xsJ = XS_LDS ? reinterpret_cast<double*>(smem_raw) : a.vJ + vo;
+  fwd_solve<TW>(base, inv, a.vJ + vo, T, xsJ, t);
+  if (tw > 0) {
+    double* xsW = XS_LDS ? reinterpret_cast<double*>(smem_raw) : a.vW + vo;
+    fwd_solve<TW>(base, inv, a.vW + vo, tw, xsW, t);
+  }
 }
 
 template <typename TW>
-__global__ __launch_bounds__(256) void k_bwd(WinVecArgs<TW> a) {
+__global__ __launch_bounds__(SOLVE_NT) void k_bwd(WinVecArgs<TW> a) {
   __shared__ double xi[TB];
   __shared__ double t[TB];
   const int m = blockIdx.x;
@@ -170,86 +213,6 @@ __global__ __launch_bounds__(256) void k_ycp(WinVecArgs<TW> a) {
   const int64_t vo = w.vec[m];
   a.vJ[vo + col] = y;
   if (col < tw * TB) a.vW[vo + col] = y;
-}
-
-// r = c' - R_X x in float64 for the rows of tile i of window m (X = J_m, and
-// X = W_m when i < tw); the covariance is recomputed from the coordinates.
-__global__ __launch_bounds__(256) void k_kmv(KmvArgs a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int d = a.d;
-  double* xr = reinterpret_cast<double*>(smem_raw);  // [d][TB]
-  double* xc = xr + d * TB;                          // [d][TB]
-  double* xvJ = xc + d * TB;                         // [TB]
-  double* xvW = xvJ + TB;                            // [TB]
-  double* part = xvW + TB;                           // [4][TB]
-  const int m = blockIdx.x, i = blockIdx.y, tid = threadIdx.x;
-  const WinTab& w = a.w;
-  const int T = w.T[m], tw = w.tw[m];
-  if (i >= T) return;
-  const int64_t vo = w.vec[m];
-  const int r = tid & (TB - 1), h = tid >> 7;
-  for (int idx = tid; idx < TB * d; idx += blockDim.x) {
-    const int rr = idx / d, tt = idx - rr * d;
-    bool v;
-    const int64_t p = win_point(w, m, i * TB + rr, v);
-    xr[tt * TB + rr] = v ? a.Xs[p * d + tt] : 0.0;
-  }
-  bool va;
-  const int64_t pa = win_point(w, m, i * TB + r, va);
-  double sj = 0.0, sw = 0.0;
-  for (int j = 0; j < T; ++j) {
-    __syncthreads();
-    for (int idx = tid; idx < TB * d; idx += blockDim.x) {
-      const int cc = idx / d, tt = idx - cc * d;
-      bool v;
-      const int64_t p = win_point(w, m, j * TB + cc, v);
-      xc[tt * TB + cc] = v ? a.Xs[p * d + tt] : 0.0;
-    }
-    if (tid < TB) {
-      bool v;
-      win_point(w, m, j * TB + tid, v);
-      xvJ[tid] = v ? a.xJ[vo + j * TB + tid] : 0.0;
-      xvW[tid] = (v && j < tw) ? a.xW[vo + j * TB + tid] : 0.0;
-    }
-    __syncthreads();
-    if (va) {
-      const bool dow = i < tw && j < tw;
-      for (int c = h; c < TB; c += 2) {
-        const double xj = xvJ[c], xw = xvW[c];
-        if (xj == 0.0 && xw == 0.0) continue;
-        double s = 0.0;
-        for (int t = 0; t < d; ++t) {
-          const double df = xr[t * TB + r] - xc[t * TB + c];
-          s += df * df;
-        }
-        const double kv = a.sf2 * exp(-0.5 * s);
-        sj += kv * xj;
-        if (dow) sw += kv * xw;
-      }
-    }
-  }
-  part[h * TB + r] = sj;
-  part[(2 + h) * TB + r] = sw;
-  __syncthreads();
-  if (tid < TB) {
-    const int row = i * TB + r;
-    double resJ = 0.0, resW = 0.0;
-    if (va) {
-      const double* vt = a.Vt + pa * a.sp;
-      const double* hj = a.hJ + (int64_t)m * a.sp;
-      const double* hw = a.hW + (int64_t)m * a.sp;
-      double qj = 0.0, qw = 0.0;
-      for (int k = 0; k < a.sp; ++k) {
-        qj += vt[k] * hj[k];
-        qw += vt[k] * hw[k];
-      }
-      const double rhs = a.rhs_pt[pa];
-      resJ = rhs - (part[r] + part[TB + r] + a.sn2 * a.xJ[vo + row] - qj);
-      if (i < tw) resW = rhs - (part[2 * TB + r] + part[3 * TB + r] + a.sn2 * a.xW[vo + row] - qw);
-    }
-    a.rJ[vo + row] = resJ;
-    if (i < tw) a.rW[vo + row] = resW;
-  }
 }
 
 __device__ inline double tiled_L(const double* L, int r, int k) {
@@ -351,72 +314,21 @@ __global__ __launch_bounds__(128) void k_h(HArgs a) {
   a.hW[(int64_t)m * a.sp + k] = hw0 + hw1;
 }
 
-// c' = c - K_DS g, one wave per training point.
-__global__ __launch_bounds__(256) void k_cg(CgArgs a) {
-  const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (i >= a.n) return;
-  const double* xi = a.Xs + i * a.d;
-  double s = 0.0;
-  for (int k = lane; k < a.s; k += 64) s += a.sf2 * exp(-0.5 * sqd(xi, a.Ss + (int64_t)k * a.d, a.d)) * a.g[k];
-  s = wave_sum(s);
-  if (lane == 0) a.out[i] = a.c[i] - s;
-}
-
-// predictive mean, one wave per test point
-__global__ __launch_bounds__(256) void k_mean(MeanArgs a) {
-  __shared__ double xu_s[4][MAX_D];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t u = (int64_t)blockIdx.x * 4 + wv;
-  const bool live = u < a.n_u;
-  if (live)
-    for (int t = lane; t < a.d; t += 64) xu_s[wv][t] = a.Us[u * a.d + t];
-  __syncthreads();
-  if (!live) return;
-  const double* xu = xu_s[wv];
-  const WinTab& w = a.w;
-  double acc = 0.0;
-  for (int k = lane; k < a.s; k += 64) acc += a.sf2 * exp(-0.5 * sqd(xu, a.Ss + (int64_t)k * a.d, a.d)) * a.g[k];
-  const int q = a.ublk[u];
-  const double* vu = a.VtU + u * a.sp;
-  for (int dl = 0; dl <= a.B && dl <= q; ++dl) {
-    const int m = q - dl;
-    const int T = w.T[m], tw = w.tw[m];
-    const int64_t vo = w.vec[m];
-    for (int r = lane; r < T * TB; r += 64) {
-      bool valid;
-      const int64_t pt = win_point(w, m, r, valid);
-      if (!valid) continue;
-      const double kv = a.sf2 * exp(-0.5 * sqd(xu, a.Xs + pt * a.d, a.d));
-      acc += kv * a.xJ[vo + r];
-      if (dl > 0 && r < tw * TB) acc -= kv * a.xW[vo + r];
-    }
-    const double* hj = a.hJ + (int64_t)m * a.sp;
-    const double* hw = a.hW + (int64_t)m * a.sp;
-    for (int k = lane; k < a.sp; k += 64) {
-      acc -= vu[k] * hj[k];
-      if (dl > 0) acc += vu[k] * hw[k];
-    }
-  }
-  acc = wave_sum(acc);
-  if (lane == 0) a.mean[u] = a.mu + acc;
-}
-
 template <typename TW>
 void launch_ycp(const WinVecArgs<TW>& a, int M, int maxT, hipStream_t st) {
   hipLaunchKernelGGL(k_ycp<TW>, dim3(M, (maxT * TB + 255) / 256), dim3(256), 0, st, a);
 }
 template <typename TW>
-void launch_fwd(const WinVecArgs<TW>& a, int M, hipStream_t st) {
-  hipLaunchKernelGGL(k_fwd<TW>, dim3(M), dim3(256), 0, st, a);
+void launch_fwd(const WinVecArgs<TW>& a, int M, int maxT, hipStream_t st) {
+  const size_t lds = sizeof(double) * (size_t)maxT * TB;
+  if (lds <= FWD_LDS_MAX)
+    hipLaunchKernelGGL((k_fwd<TW, true>), dim3(M), dim3(SOLVE_NT), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_fwd<TW, false>), dim3(M), dim3(SOLVE_NT), 0, st, a);
 }
 template <typename TW>
 void launch_bwd(const WinVecArgs<TW>& a, int M, hipStream_t st) {
-  hipLaunchKernelGGL(k_bwd<TW>, dim3(M), dim3(256), 0, st, a);
-}
-void launch_kmv(const KmvArgs& a, int M, int maxT, hipStream_t st) {
-  const size_t lds = sizeof(double) * (size_t)(2 * a.d * TB + 6 * TB);
-  hipLaunchKernelGGL(k_kmv, dim3(M, maxT), dim3(256), lds, st, a);
+  hipLaunchKernelGGL(k_bwd<TW>, dim3(M), dim3(SOLVE_NT), 0, st, a);
 }
 void launch_gres(const GresArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_gres, dim3(1), dim3(256), sizeof(double) * (size_t)a.sp, st, a);
@@ -438,22 +350,18 @@ void launch_axpy2(double* vJ, double* vW, const double* xJ, const double* xW, do
 void launch_h(const HArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(k_h, dim3(a.M, a.sp / TB), dim3(TB), 0, st, a);
 }
-void launch_cg(const CgArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, st, a);
-}
-void launch_mean(const MeanArgs& a, hipStream_t st) {
-  if (a.n_u <= 0) return;
-  hipLaunchKernelGGL(k_mean, dim3((unsigned)((a.n_u + 3) / 4)), dim3(256), 0, st, a);
-}
 hipError_t vecsolve_init() {
-  return hipFuncSetAttribute((const void*)k_kmv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(sizeof(double) * (2 * MAX_D * TB + 6 * TB)));
+  for (const void* f : {(const void*)k_fwd<double, true>, (const void*)k_fwd<float, true>}) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)FWD_LDS_MAX);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template void launch_ycp<double>(const WinVecArgs<double>&, int, int, hipStream_t);
 template void launch_ycp<float>(const WinVecArgs<float>&, int, int, hipStream_t);
-template void launch_fwd<double>(const WinVecArgs<double>&, int, hipStream_t);
-template void launch_fwd<float>(const WinVecArgs<float>&, int, hipStream_t);
+template void launch_fwd<double>(const WinVecArgs<double>&, int, int, hipStream_t);
+template void launch_fwd<float>(const WinVecArgs<float>&, int, int, hipStream_t);
 template void launch_bwd<double>(const WinVecArgs<double>&, int, hipStream_t);
 template void launch_bwd<float>(const WinVecArgs<float>&, int, hipStream_t);
 
