@@ -248,8 +248,14 @@ def summarise(rows, cap):
     return {"sets": len(rows), "median_steps_default": float(np.median(kd)), "median_steps_net": float(np.median(kn)),
             "mean_steps_default": float(np.mean(kd)), "mean_steps_net": float(np.mean(kn)),
             "win_rate": float(np.mean(kn < kd)), "ties": float(np.mean(kn == kd)),
-            "median_seconds_default": float(np.nanmedian(td)), "median_seconds_net": float(np.nanmedian(tn)),
+            "median_seconds_default": _nanmedian(td), "median_seconds_net": _nanmedian(tn),
             "fallbacks": int(sum(r["fallback"] for r in rows)), "step_cap": cap}
+
+
+def _nanmedian(v):
+    """Median over the sets that reached the target; None when none did."""
+    v = v[np.isfinite(v)]
+    return float(np.median(v)) if v.size else None
 
 
 def cmd_evaluate(a):
