@@ -5,14 +5,16 @@
 // its Cholesky factor on the fly: for RHS rows b the engine produces
 // b L^-T, i.e. rows of (L^-1 b^T)^T.  Every entry of the matrix and of the
 // right-hand sides is generated inside the update kernel (covariance tile,
-// explicit matrix, or the centred output vector) and corrected by
+// explicit matrix, the centred output vector, or a read of the residual band)
+// and corrected by
 //
 //   C_ij = K_ij - V_i V_j^T - sum_{k<j} L_ik L_jk^T
 //
 // where V rows are the whitened support rows V^T = K_XS L_SS^-T of the
 // points of the tile (present only when both tiles carry them).  The V term
-// turns the covariance into the residual R = Sigma - Q of the paper, so the
-// residual matrix is never stored.
+// turns the covariance into the residual R = Sigma - Q of the paper.  For the
+// overlapping windows of the fit, K_ij - V_i V_j^T (with the noise) is formed
+// once per point pair into the residual band and read from there.
 //
 // All problems of one run advance column by column in lock step: for column
 // tile j one update launch covers every row tile i >= j of every problem
@@ -31,7 +33,12 @@ constexpr int DIAG_LD = TB + 1;
 // SRC_IDENT: the right-hand-side rows are rows kbeg*TB .. kbeg*TB+127 of the
 // identity, so the solve produces the matching rows of L^-T (an explicit
 // inverse factor); such a row is zero left of column tile kbeg.
-enum Src : int32_t { SRC_KERNEL = 0, SRC_EXPLICIT = 1, SRC_CVEC = 2, SRC_IDENT = 3 };
+// SRC_BAND: matrix rows whose entries K_pq + noise - V_p.V_q are read from the
+// precomputed residual band (StepArgs::band, filled by launch_band): windows
+// overlap, so each point pair of the band is formed once instead of once per
+// window that holds it.  Row and column tiles are runs of consecutive
+// training points starting at pt0.
+enum Src : int32_t { SRC_KERNEL = 0, SRC_EXPLICIT = 1, SRC_CVEC = 2, SRC_IDENT = 3, SRC_BAND = 4 };
 
 template <typename T>
 struct RowTile {
@@ -50,6 +57,7 @@ struct RowTile {
   int32_t is_j;      // 1 for rows of the matrix being factored
   int32_t kbeg;      // first column tile stored (the row is zero to its left); 0 except SRC_IDENT
   int32_t pad_;
+  int64_t pt0;       // SRC_BAND: training index of the tile's first row
 };
 
 struct ProbDesc {
@@ -80,7 +88,40 @@ struct StepArgs {
   double* logdiag;    // [problem][maxT]
   int32_t* status;    // [problem], set to 1 when a pivot is not positive
   int32_t maxT;
+  // residual band of the SRC_BAND rows: entry (p, q) with q <= p at band[brow[p] + q]
+  // (the other triangle by symmetry); null when no row of the run uses it
+  const T* band;
+  const int64_t* brow;
 };
+
+// Residual band: for training point p in block a, the entries
+//   R_pq = sf2 exp(-|x_p - x_q|^2 / 2) + [p == q] sn2 - V_p . V_q
+// for q from the first point of block max(0, a - B) up to p, stored in a
+// row-major panel per block (the part of the panel right of p is not read).
+// One item is a 128 x 128 tile of such a panel; k_band forms it with the V
+// products on the float64 matrix cores and the covariance in float64, and
+// rounds once to the storage type.
+struct BandItem {
+  int64_t p0, q0;   // first row / column training point
+  int64_t off;      // element offset of entry (p0, q0) in the band
+  int64_t ld;       // panel row stride (elements)
+  int32_t nr, nc;   // valid rows / columns
+};
+template <typename T>
+struct BandArgs {
+  const BandItem* items;
+  int32_t nitems;
+  int32_t d;
+  int32_t vlen;       // length of the whitened support rows (multiple of 16)
+  int32_t pad_;
+  int64_t vld;
+  const double* Vt;   // whitened support rows [n][vld]
+  const double* Xs;   // length-scaled coordinates [n][d]
+  double sf2, sn2;
+  T* band;
+};
+template <typename T>
+void launch_band(const BandArgs<T>& a, hipStream_t st);
 
 // Host-side launchers (engine.hip).
 // mixed = true (float storage only): the covariance tile and the V_i V_j^T

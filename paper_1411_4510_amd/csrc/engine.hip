@@ -29,7 +29,8 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
   if constexpr (MIXED) zero_acc<T>(accl);
   const TK* vi = MIXED ? (const TK*)ri.vt64 : (const TK*)ri.vt;
   const TK* vj = MIXED ? (const TK*)rj.vt64 : (const TK*)rj.vt;
-  if (vi != nullptr && vj != nullptr && a.vlen > 0)
+  const bool band = ri.src == SRC_BAND;  // V part already inside the band entries
+  if (!band && vi != nullptr && vj != nullptr && a.vlen > 0)
     wave_gemm<TK, TK>(accv, vi, a.vld, ri.nvalid, vj, a.vld, rj.nvalid, 0, a.vlen, wr * 64, wc * 64, lane);
   // factor columns kb .. j-1 (a row is zero left of its kbeg)
   const int kb = ri.kbeg > rj.kbeg ? ri.kbeg : rj.kbeg;
@@ -82,6 +83,9 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
             }
             kv = sf2 * k_exp(TK(-0.5) * s);
             if (diag && row == col) kv += sn2;
+          } else if (band) {
+            const int64_t p = ri.pt0 + row, q = rj.pt0 + col;
+            kv = (TK)(q <= p ? a.band[a.brow[p] + q] : a.band[a.brow[q] + p]);
           } else if (ri.src == SRC_EXPLICIT) {
             kv = (TK)ri.expl[(int64_t)row * ri.eld + (int64_t)a.j * TB + col];
           } else {
@@ -276,6 +280,52 @@ __global__ __launch_bounds__(NT) void k_tile_gemm(const GemmTerm<T>* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// band: R_pq = K_pq + [p == q] sn2 - V_p . V_q on one 128 x 128 tile of the
+// residual band (float64 arithmetic, one rounding to T on the store)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(NT) void k_band(BandArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int logical = xcd_logical(blockIdx.x, gridDim.x);
+  if (logical >= a.nitems) return;
+  const BandItem it = a.items[logical];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
+  // coordinates first: their loads complete while the V products run
+  const int d = a.d;
+  double* xr = reinterpret_cast<double*>(smem_raw);  // [d][TB]
+  double* xc = xr + d * TB;
+  for (int idx = tid; idx < TB * d; idx += NT) {
+    const int r = idx / d, t = idx - r * d;
+    xr[t * TB + r] = r < it.nr ? a.Xs[(it.p0 + r) * d + t] : 0.0;
+    xc[t * TB + r] = r < it.nc ? a.Xs[(it.q0 + r) * d + t] : 0.0;
+  }
+  typename Mfma<double>::acc acc[4][4];
+  zero_acc<double>(acc);
+  wave_gemm<double, double>(acc, a.Vt + it.p0 * a.vld, a.vld, it.nr, a.Vt + it.q0 * a.vld, a.vld, it.nc, 0, a.vlen,
+                            wr * 64, wc * 64, lane);
+  __syncthreads();
+#pragma unroll
+  for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 64 + rs * 16 + Mfma<double>::row(lane, v);
+        const int col = wc * 64 + cs * 16 + (lane & 15);
+        if (row < it.nr && col < it.nc) {
+          double sq = 0.0;
+          for (int t = 0; t < d; ++t) {
+            const double df = xr[t * TB + row] - xc[t * TB + col];
+            sq += df * df;
+          }
+          double kv = a.sf2 * k_exp(-0.5 * sq);
+          if (it.p0 + row == it.q0 + col) kv += a.sn2;
+          a.band[it.off + (int64_t)row * it.ld + col] = (T)(kv - acc[rs][cs][v]);
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 static inline int pad8(int n) { return ((n + 7) / 8) * 8; }
@@ -314,6 +364,12 @@ void launch_trsm(const StepArgs<T>& a, hipStream_t st) {
 }
 
 template <typename T>
+void launch_band(const BandArgs<T>& a, hipStream_t st) {
+  if (a.nitems <= 0) return;
+  hipLaunchKernelGGL(k_band<T>, dim3(pad8(a.nitems)), dim3(NT), 2 * (size_t)a.d * TB * sizeof(double), st, a);
+}
+
+template <typename T>
 void launch_tile_gemm(const GemmTerm<T>* terms, const GemmOut* outs, int nout, hipStream_t st) {
   if (nout <= 0) return;
   hipLaunchKernelGGL(k_tile_gemm<T>, dim3(pad8(nout)), dim3(NT), 0, st, terms, outs, nout);
@@ -333,8 +389,14 @@ hipError_t engine_init() {
   e = hipFuncSetAttribute((const void*)k_update<float, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(2 * 64 * TB * sizeof(double)));
   if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_update<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)(2 * 64 * TB * sizeof(float)));
+  e = hipFuncSetAttribute((const void*)k_update<float, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(2 * 64 * TB * sizeof(float)));
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_band<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(2 * 64 * TB * sizeof(double)));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_band<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(2 * 64 * TB * sizeof(double)));
 }
 
 template void launch_update<double>(const StepArgs<double>&, bool, hipStream_t);
@@ -343,6 +405,8 @@ template void launch_diag<double>(const StepArgs<double>&, const int32_t*, int, 
 template void launch_diag<float>(const StepArgs<float>&, const int32_t*, int, hipStream_t);
 template void launch_trsm<double>(const StepArgs<double>&, hipStream_t);
 template void launch_trsm<float>(const StepArgs<float>&, hipStream_t);
+template void launch_band<double>(const BandArgs<double>&, hipStream_t);
+template void launch_band<float>(const BandArgs<float>&, hipStream_t);
 template void launch_tile_gemm<double>(const GemmTerm<double>*, const GemmOut*, int, hipStream_t);
 template void launch_tile_gemm<float>(const GemmTerm<float>*, const GemmOut*, int, hipStream_t);
 

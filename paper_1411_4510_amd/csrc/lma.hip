@@ -18,10 +18,12 @@
 // Sigma_ddot solve of k_u - G_u, and the combine of Theorem 2.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <type_traits>
@@ -40,10 +42,10 @@ thread_local int64_t g_failed = 0;
 
 namespace lmart {
 
-// Device blocks released by lma_free / lma_predict are kept (at most two) and
-// reused by the next call that fits in them: a state at the n=524288
-// workload is ~95 GB and mapping it anew each fit costs a few hundred
-// milliseconds.  lma_release_cache() returns them to the runtime.
+// Device blocks released by lma_free / lma_predict / the end of a fit are
+// kept (at most four) and reused by the next call that fits in them: a state
+// at the n=524288 workload is ~95 GB and mapping it anew each fit costs a few
+// hundred milliseconds.  lma_release_cache() returns them to the runtime.
 namespace devcache {
 struct Block {
   void* p = nullptr;
@@ -51,27 +53,46 @@ struct Block {
   int device = -1;
 };
 std::mutex mu;
-Block slots[2];
+constexpr int NSLOT = 4;
+Block slots[NSLOT];
+// real size of every block handed out (a cached block can be larger than the
+// request it served; it returns to the cache with its real size)
+std::map<void*, size_t> out_sizes;
+// LMA_CACHE_TRACE=1 prints every cache decision with its host time (stderr)
+bool trace() {
+  static const bool on = std::getenv("LMA_CACHE_TRACE") != nullptr;
+  return on;
+}
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
 void free_all_locked() {
+  const double t0 = trace() ? now_s() : 0.0;
+  size_t freed = 0;
   for (Block& b : slots) {
     if (b.p) (void)hipFree(b.p);
+    freed += b.bytes;
     b = Block{};
   }
+  if (trace()) fprintf(stderr, "[devcache] free all: %.2f GB in %.3f s\n", freed / 1e9, now_s() - t0);
 }
 void* get(size_t bytes) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(mu);
   int best = -1;
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NSLOT; ++i)
     if (slots[i].p && slots[i].device == dev && slots[i].bytes >= bytes && slots[i].bytes <= 2 * bytes + (64 << 20) &&
         (best < 0 || slots[i].bytes < slots[best].bytes))
       best = i;
   if (best >= 0) {
     void* p = slots[best].p;
+    if (trace()) fprintf(stderr, "[devcache] get %.2f GB: cached block of %.2f GB\n", bytes / 1e9, slots[best].bytes / 1e9);
+    out_sizes[p] = slots[best].bytes;
     slots[best] = Block{};
     return p;
   }
+  const double t0 = trace() ? now_s() : 0.0;
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess || !p) {
     (void)hipGetLastError();
@@ -82,6 +103,8 @@ void* get(size_t bytes) {
       return nullptr;
     }
   }
+  if (trace()) fprintf(stderr, "[devcache] get %.2f GB: hipMalloc in %.3f s\n", bytes / 1e9, now_s() - t0);
+  out_sizes[p] = bytes;
   return p;
 }
 void put(void* p, size_t bytes) {
@@ -89,15 +112,25 @@ void put(void* p, size_t bytes) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lk(mu);
+  const auto known = out_sizes.find(p);
+  if (known != out_sizes.end()) {
+    bytes = known->second;
+    out_sizes.erase(known);
+  }
   int victim = 0;
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NSLOT; ++i)
     if (!slots[i].p) {
       victim = i;
       break;
     } else if (slots[i].bytes < slots[victim].bytes) {
       victim = i;
     }
-  if (slots[victim].p) (void)hipFree(slots[victim].p);
+  if (slots[victim].p) {
+    const double t0 = trace() ? now_s() : 0.0;
+    (void)hipFree(slots[victim].p);
+    if (trace()) fprintf(stderr, "[devcache] evict %.2f GB in %.3f s\n", slots[victim].bytes / 1e9, now_s() - t0);
+  }
+  if (trace()) fprintf(stderr, "[devcache] put %.2f GB\n", bytes / 1e9);
   slots[victim] = Block{p, bytes, dev};
 }
 void release() {
@@ -205,13 +238,13 @@ void set_err(const Err& e) {
 // ---------------------------------------------------------------------------
 template <typename TW>
 void build_window_run(lma_state& f, Run<TW>& run, TW* winbase, const double* Xs, const double* Vt, const TW* c,
-                      const double* Ss) {
+                      const double* Ss, bool band) {
   const int Ts = (int)f.Ts;
   for (int64_t m = 0; m < f.M; ++m) {
     const WinGeom g = win_geom(f.bp, f.M, f.B, m);
     TW* base = winbase + f.win_off[m];
     run.add_problem(g.T, Ts + 1, g.tw, false, (int)m);
-    add_window_jtiles<TW>(run.rt, g, base, Xs, Vt, c, f.d, f.sp);
+    add_window_jtiles<TW>(run.rt, g, base, Xs, Vt, c, f.d, f.sp, band);
     TW* rhs = base + jpanel_off(g.T);
     const int64_t ld = (int64_t)g.T * TB;
     for (int r = 0; r < Ts; ++r) {
@@ -264,6 +297,26 @@ void build_summary(lma_state& f, std::vector<GemmTerm<TW>>& terms, TW* winbase) 
       }
   }
 }
+
+// Residual band of one fit: one device block [band | items | row offsets]
+// from the device cache, returned when the fit ends, after the stream has
+// drained (its kernels may still read it when an error ends the fit early).
+struct BandPlan {
+  std::vector<BandItem> items;
+  std::vector<int64_t> brow;
+  int64_t o_items = 0, o_brow = 0, bytes = 0;
+  void* mem = nullptr;
+  hipStream_t st = nullptr;
+  BandPlan() = default;
+  BandPlan(const BandPlan&) = delete;
+  BandPlan& operator=(const BandPlan&) = delete;
+  ~BandPlan() {
+    if (mem) {
+      (void)hipStreamSynchronize(st);
+      devcache::put(mem, (size_t)bytes);
+    }
+  }
+};
 
 lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool keep) {
   check_problem(p);
@@ -348,6 +401,37 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     f.o_rho = ar.reserve(8 * sp);
   }
 
+  // ---- residual band (overlapping windows only): panel of block a spans the
+  // points of blocks max(0, a-B) .. a; tiles entirely right of the diagonal
+  // are never read and not formed
+  BandPlan bpl;
+  bool use_band = f.B >= 1 && std::getenv("LMA_NO_BAND") == nullptr;
+  if (use_band) {
+    bpl.brow.resize(n);
+    int64_t off = 0;
+    for (int64_t a = 0; a < M; ++a) {
+      const int64_t c0 = f.bp[std::max<int64_t>(0, a - f.B)], r0 = f.bp[a], r1 = f.bp[a + 1], w = r1 - c0;
+      for (int64_t p = r0; p < r1; ++p) bpl.brow[p] = off + (p - r0) * w - c0;
+      for (int64_t p0 = r0; p0 < r1; p0 += TB) {
+        const int nr = (int)std::min<int64_t>(TB, r1 - p0);
+        for (int64_t q0 = c0; q0 < r1 && q0 <= p0 + nr - 1; q0 += TB) {
+          BandItem it;
+          it.p0 = p0;
+          it.q0 = q0;
+          it.off = off + (p0 - r0) * w + (q0 - c0);
+          it.ld = w;
+          it.nr = nr;
+          it.nc = (int)std::min<int64_t>(TB, r1 - q0);
+          bpl.items.push_back(it);
+        }
+      }
+      off += (r1 - r0) * w;
+    }
+    bpl.o_items = align_up(wsz * off, 256);
+    bpl.o_brow = bpl.o_items + align_up((int64_t)sizeof(BandItem) * (int64_t)bpl.items.size(), 256);
+    bpl.bytes = bpl.o_brow + 8 * n;
+  }
+
   // engine runs (built with arena offsets; pointers fixed after allocation)
   // Reserve space for run metadata: build runs against a null base first to size them.
   auto build_runs = [&](char* base) {
@@ -370,12 +454,12 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     // window run
     if (mixed) {
       build_window_run<float>(f, f.runW32, f.ptr<float>(f.o_win), f.ptr<double>(f.o_Xs64), f.ptr<double>(f.o_Vt64),
-                              f.ptr<float>(f.o_c32), f.ptr<double>(f.o_Ss64));
+                              f.ptr<float>(f.o_c32), f.ptr<double>(f.o_Ss64), use_band);
       f.runW32.schedule();
       build_summary<float>(f, f.sum32, f.ptr<float>(f.o_win));
     } else {
       build_window_run<double>(f, f.runW64, f.ptr<double>(f.o_win), f.ptr<double>(f.o_Xs64),
-                               f.ptr<double>(f.o_Vt64), f.ptr<double>(f.o_c64), f.ptr<double>(f.o_Ss64));
+                               f.ptr<double>(f.o_Vt64), f.ptr<double>(f.o_c64), f.ptr<double>(f.o_Ss64), use_band);
       f.runW64.schedule();
       build_summary<double>(f, f.sum64, f.ptr<double>(f.o_win));
     }
@@ -442,6 +526,7 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   f.o_sumterms = ar.reserve(sterm_bytes);
   f.o_sumout = ar.reserve(sizeof(GemmOut) * f.sumout.size());
   f.ar.cap = f.ar.used;
+  if (use_band && p->mem_budget_bytes > 0 && f.ar.cap + bpl.bytes > p->mem_budget_bytes) use_band = false;
   if (p->mem_budget_bytes > 0 && f.ar.cap > p->mem_budget_bytes) {
     char buf[160];
     snprintf(buf, sizeof buf, "state needs %lld bytes, over the budget of %lld", (long long)f.ar.cap,
@@ -456,6 +541,11 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       throw Err{LMA_E_NOMEM, buf};
     }
     f.ar.used = f.ar.cap;
+    if (use_band) {
+      bpl.mem = devcache::get((size_t)bpl.bytes);
+      bpl.st = st;
+      if (!bpl.mem) use_band = false;  // not enough device memory: windows form their entries themselves
+    }
     build_runs(reinterpret_cast<char*>(mem));
   }
   // ---- upload schedules
@@ -471,6 +561,12 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       mp += f.runW64.meta_bytes();
     }
     f.runD.upload(mp, st);
+    if (use_band) {
+      char* bm = static_cast<char*>(bpl.mem);
+      HIPCHK(hipMemcpyAsync(bm + bpl.o_items, bpl.items.data(), sizeof(BandItem) * bpl.items.size(),
+                            hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(bm + bpl.o_brow, bpl.brow.data(), 8 * n, hipMemcpyHostToDevice, st));
+    }
     if (mixed)
       HIPCHK(hipMemcpyAsync(f.ptr<char>(f.o_sumterms), f.sum32.data(), sterm_bytes, hipMemcpyHostToDevice, st));
     else
@@ -498,10 +594,14 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   HIPCHK(hipGetLastError());
   const int maxTld = (int)(f.n_logdiag / (M + 2));
   // Runs share one logdiag stride (maxTld); set it before executing.
-  auto run_with_stride = [&](auto& run, auto* invdiag, int slot, int vlen) {
+  auto run_with_stride = [&](auto& run, auto* invdiag, int slot, int vlen, bool with_band) {
     const int realT = run.maxT;
     using TT = typename std::remove_pointer<decltype(invdiag)>::type;
-    StepArgs<TT> a;
+    StepArgs<TT> a{};
+    if (with_band) {
+      a.band = reinterpret_cast<const TT*>(bpl.mem);
+      a.brow = reinterpret_cast<const int64_t*>(static_cast<char*>(bpl.mem) + bpl.o_brow);
+    }
     a.rt = run.d_rt;
     a.pd = run.d_pd;
     a.vlen = vlen;
@@ -529,12 +629,37 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       HIPCHK(hipGetLastError());
     }
   };
-  run_with_stride(f.runS, f.ptr<double>(f.o_Lss_inv), (int)M, 0);
+  run_with_stride(f.runS, f.ptr<double>(f.o_Lss_inv), (int)M, 0, false);
+  if (use_band) {
+    auto band_launch = [&](auto* band) {
+      using TT = typename std::remove_pointer<decltype(band)>::type;
+      BandArgs<TT> ba{};
+      ba.items = reinterpret_cast<const BandItem*>(static_cast<char*>(bpl.mem) + bpl.o_items);
+      ba.nitems = (int32_t)bpl.items.size();
+      ba.d = (int)d;
+      ba.vlen = (int)sp;
+      ba.vld = sp;
+      ba.Vt = f.ptr<double>(f.o_Vt64);
+      ba.Xs = f.ptr<double>(f.o_Xs64);
+      ba.sf2 = f.sf2;
+      ba.sn2 = f.sn2;
+      ba.band = band;
+      double fl = 0.0;
+      if (prof::on)
+        for (const BandItem& it : bpl.items) fl += 2.0 * it.nr * it.nc * (double)s;
+      prof::timed(prof::GEMM, fl, st, [&] { launch_band<TT>(ba, st); });
+      HIPCHK(hipGetLastError());
+    };
+    if (mixed)
+      band_launch(static_cast<float*>(bpl.mem));
+    else
+      band_launch(static_cast<double*>(bpl.mem));
+  }
   if (mixed) {
-    run_with_stride(f.runW32, f.ptr<float>(f.o_win_inv), 0, (int)sp);
+    run_with_stride(f.runW32, f.ptr<float>(f.o_win_inv), 0, (int)sp, use_band);
     prof::timed(prof::GEMM, prof::on ? gemm_flops(f.sum32, f.sumout, 0, (int64_t)f.sumout.size()) : 0.0, st, [&] { launch_tile_gemm<float>(reinterpret_cast<const GemmTerm<float>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
   } else {
-    run_with_stride(f.runW64, f.ptr<double>(f.o_win_inv), 0, (int)sp);
+    run_with_stride(f.runW64, f.ptr<double>(f.o_win_inv), 0, (int)sp, use_band);
     prof::timed(prof::GEMM, prof::on ? gemm_flops(f.sum64, f.sumout, 0, (int64_t)f.sumout.size()) : 0.0, st, [&] { launch_tile_gemm<double>(reinterpret_cast<const GemmTerm<double>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
   }
   HIPCHK(hipGetLastError());
@@ -556,7 +681,7 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     prof::timed(prof::OTHER, 0.0, st, [&] { launch_finalize_summary(sa, st); });
     HIPCHK(hipGetLastError());
   }
-  run_with_stride(f.runD, f.ptr<double>(f.o_Ldd_inv), (int)M + 1, 0);
+  run_with_stride(f.runD, f.ptr<double>(f.o_Ldd_inv), (int)M + 1, 0, false);
   {
     SolveArgs so;
     so.L = f.ptr<double>(f.o_Ldd);
@@ -1032,7 +1157,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   HIPCHK(hipGetLastError());
   auto exec = [&](auto& run, auto* invdiag, int vlen) {
     using TT = typename std::remove_pointer<decltype(invdiag)>::type;
-    StepArgs<TT> a;
+    StepArgs<TT> a{};
     a.rt = run.d_rt;
     a.pd = run.d_pd;
     a.vlen = vlen;

@@ -77,7 +77,7 @@ void add_ex(DcItem& it, const double* e, int64_t ld, double s) {
 // solve-only steps of an engine run (right-hand sides only)
 template <typename TT>
 void solve_steps(Run<TT>& run, TT* invdiag, const lma_state& f, double* ldg, int32_t* stat, hipStream_t st) {
-  StepArgs<TT> a;
+  StepArgs<TT> a{};
   a.rt = run.d_rt;
   a.pd = run.d_pd;
   a.vlen = 0;

@@ -195,7 +195,7 @@ struct Run {
       const ProbDesc& p = pd[it.p];
       const RowTile<T>& ri = rt[p.first + it.tile];
       const RowTile<T>& rj = rt[p.first + j];
-      const double Kv = (ri.vt64 && rj.vt64) ? (double)s_valid : 0.0;
+      const double Kv = (ri.vt64 && rj.vt64 && ri.src != SRC_BAND) ? (double)s_valid : 0.0;
       const double K = Kv + (double)(cum_nvalid[p.first + j] - cum_nvalid[p.first + std::min(ri.kbeg, j)]);
       const double rows = ri.nvalid, cols = rj.nvalid;
       const double pairs = (ri.is_j && it.tile == j) ? rows * (rows + 1) / 2 : rows * cols;
@@ -314,6 +314,7 @@ RowTile<T> make_tile(T* panel, int64_t ld, const T* vt, const T* xs, const T* cv
   r.is_j = is_j;
   r.kbeg = 0;
   r.pad_ = 0;
+  r.pt0 = 0;
   r.vt64 = std::is_same<T, double>::value ? reinterpret_cast<const double*>(vt) : nullptr;
   r.xs64 = std::is_same<T, double>::value ? reinterpret_cast<const double*>(xs) : nullptr;
   return r;
@@ -391,7 +392,7 @@ inline KvItem kv_item(const double* x, int nr, int c0, int c1) {
 // (float runs use them through vt64 / xs64 in the mixed update kernel).
 template <typename T>
 void add_window_jtiles(std::vector<RowTile<T>>& rt, const WinGeom& g, T* base, const double* Xs, const double* Vt,
-                       const T* c, int64_t d, int64_t sp) {
+                       const T* c, int64_t d, int64_t sp, bool band = false) {
   for (int i = 0; i < g.T; ++i) {
     int64_t pt;
     int nv;
@@ -408,6 +409,10 @@ void add_window_jtiles(std::vector<RowTile<T>>& rt, const WinGeom& g, T* base, c
                                 f64 ? reinterpret_cast<const T*>(Xs + pt * d) : nullptr, c + pt, nv, TB, SRC_KERNEL, 1);
     t.vt64 = Vt + pt * sp;
     t.xs64 = Xs + pt * d;
+    if (band) {
+      t.src = SRC_BAND;
+      t.pt0 = pt;
+    }
     rt.push_back(t);
   }
 }

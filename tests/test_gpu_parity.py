@@ -65,6 +65,29 @@ def test_config0(lib, precision):
     check(lib, synth.make_config(0), precision)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_band_and_on_the_fly_entries_agree(lib, monkeypatch, precision):
+    """Windows that read their residual entries from the shared band (the
+    default when B >= 1) and windows that form them in the update kernel
+    (LMA_NO_BAND) give the same fit: both within the oracle bar, and within
+    rounding of each other."""
+    p = synth.make_random(seed=17, n=2600, d=4, M=6, s=150, n_u=300, B=2, uneven=(150, 650),
+                          ell_range=(0.3, 1.5), sn2=0.02, name="band")
+    ref = olma.fit_predict(p)
+    a = gpu_fit_predict(lib, p, precision)
+    monkeypatch.setenv("LMA_NO_BAND", "1")
+    b = gpu_fit_predict(lib, p, precision)
+    monkeypatch.delenv("LMA_NO_BAND")
+    for out in (a, b):
+        assert rel(out[0], ref["mean"]) <= TOL[precision] and rel(out[1], ref["var"]) <= TOL[precision]
+        assert abs(out[2] - ref["lml"]) <= TOL[precision] * abs(ref["lml"])
+    agree = {"fp64": 1e-12, "mixed": 1e-6}[precision]
+    print(f"  band vs on-the-fly: mean {rel(a[0], b[0]):.2e} var {rel(a[1], b[1]):.2e} "
+          f"lml {abs(a[2] - b[2]) / abs(b[2]):.2e}", flush=True)
+    assert rel(a[0], b[0]) <= agree and rel(a[1], b[1]) <= agree
+    assert abs(a[2] - b[2]) <= agree * abs(b[2])
+
+
 def test_fp64_is_deterministic(lib):
     p = synth.make_random(seed=5, n=900, d=3, M=5, s=70, n_u=100, B=2, uneven=(100, 250))
     a = gpu_fit_predict(lib, p, "fp64")
