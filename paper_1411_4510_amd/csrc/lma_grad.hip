@@ -253,7 +253,7 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, T
   std::vector<DcItem> items;
   std::vector<GemmTerm<TW>> x_terms;
   GemmBatch prepB, finB;
-  std::vector<GemmBatch> c2(nchunk), c3(nchunk), c4(nchunk);
+  std::vector<GemmBatch> c2(nchunk), c2b(nchunk), c3(nchunk), c4(nchunk);
   std::vector<int64_t> it_beg(nchunk + 2);
 
   auto build = [&](char* base) {
@@ -352,44 +352,79 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, T
         }
       }
       run.schedule();
-      // Gamma_J = X_J Y_J, Gamma_W = X_W Y_W, G0_J = Y_J^T Y_J, G0_W = Y_W^T Y_W
+      // Gamma_W = X_W Y_W and G0_W = Y_W^T Y_W first.  X_W and Y_W are the leading
+      // blocks of X_J and Y_J (W_m leads the window order), so the J products then
+      // reuse them: Gamma_J rows i < tw = Gamma_W + X[i, tw:T] Y[tw:T] and
+      // G0_J = G0_W + Y_D^T Y_D.
       c2[c].o0 = (int64_t)outs_tw.size();
       for (int64_t m = cbeg[c]; m < cbeg[c + 1]; ++m) {
         const WinGeom& g = geo[m];
         const TW* Xm = reinterpret_cast<const TW*>(reinterpret_cast<char*>(Xb) + xoff[m]);
         const TW* R = winbase + f.win_off[m] + jpanel_off(g.T);
         const int64_t ldR = (int64_t)g.T * TB;
-        double* GJ = Db + goff[m];
         double* GW = Db + gwoff[m];
-        double* G0J = Db + soff[m];
-        double* G0W = G0J + sp2;
-        for (int i = 0; i < g.T; ++i)
-          for (int t = 0; t < Ts; ++t)
-            for (int w = 0; w < 2; ++w) {
-              if (w && i >= g.tw) continue;
-              const int kend = w ? g.tw : g.T;
-              GemmOut o = gemm_out((w ? GW : GJ) + (int64_t)i * TB * sp + (int64_t)t * TB, sp, TB, TB, 0,
-                                   (int)tw_terms.size());
-              tw_terms.push_back(term<TW>(Xm + tri_off(g.T, i), (int64_t)(g.T - i) * TB, TB,
-                                          R + (int64_t)t * TB * ldR + (int64_t)i * TB, ldR, TB,
-                                          (int64_t)(kend - i) * TB));
-              o.t1 = (int32_t)tw_terms.size();
-              outs_tw.push_back(o);
-            }
-        for (int pa = 0; pa < Ts; ++pa)
-          for (int pb = 0; pb < Ts; ++pb)
-            for (int w = 0; w < 2; ++w) {
-              const int kend = w ? g.tw : g.T;
-              if (kend == 0) continue;
-              GemmOut o = gemm_out((w ? G0W : G0J) + (int64_t)pa * TB * sp + (int64_t)pb * TB, sp, TB, TB, 0,
-                                   (int)tw_terms.size());
+        double* G0W = Db + soff[m] + sp2;
+        for (int i = 0; i < g.tw; ++i)
+          for (int t = 0; t < Ts; ++t) {
+            GemmOut o = gemm_out(GW + (int64_t)i * TB * sp + (int64_t)t * TB, sp, TB, TB, 0, (int)tw_terms.size());
+            tw_terms.push_back(term<TW>(Xm + tri_off(g.T, i), (int64_t)(g.T - i) * TB, TB,
+                                        R + (int64_t)t * TB * ldR + (int64_t)i * TB, ldR, TB,
+                                        (int64_t)(g.tw - i) * TB));
+            o.t1 = (int32_t)tw_terms.size();
+            outs_tw.push_back(o);
+          }
+        if (g.tw > 0)
+          for (int pa = 0; pa < Ts; ++pa)
+            for (int pb = 0; pb < Ts; ++pb) {
+              GemmOut o = gemm_out(G0W + (int64_t)pa * TB * sp + (int64_t)pb * TB, sp, TB, TB, 0, (int)tw_terms.size());
               tw_terms.push_back(term<TW>(R + (int64_t)pa * TB * ldR, ldR, TB, R + (int64_t)pb * TB * ldR, ldR, TB,
-                                          (int64_t)kend * TB));
+                                          (int64_t)g.tw * TB));
               o.t1 = (int32_t)tw_terms.size();
               outs_tw.push_back(o);
             }
       }
       c2[c].o1 = (int64_t)outs_tw.size();
+      c2b[c].o0 = (int64_t)outs_tw.size();
+      for (int64_t m = cbeg[c]; m < cbeg[c + 1]; ++m) {
+        const WinGeom& g = geo[m];
+        const TW* Xm = reinterpret_cast<const TW*>(reinterpret_cast<char*>(Xb) + xoff[m]);
+        const TW* R = winbase + f.win_off[m] + jpanel_off(g.T);
+        const int64_t ldR = (int64_t)g.T * TB;
+        double* GJ = Db + goff[m];
+        const double* GW = Db + gwoff[m];
+        double* G0J = Db + soff[m];
+        const double* G0W = G0J + sp2;
+        for (int i = 0; i < g.T; ++i)
+          for (int t = 0; t < Ts; ++t) {
+            const int k0 = i < g.tw ? g.tw : i;  // first column of X row i still to add
+            GemmOut o = gemm_out(GJ + (int64_t)i * TB * sp + (int64_t)t * TB, sp, TB, TB, 0, (int)tw_terms.size());
+            if (i < g.tw) {
+              o.c = GW + (int64_t)i * TB * sp + (int64_t)t * TB;
+              o.ldc = sp;
+              o.beta = 1.0;
+            }
+            tw_terms.push_back(term<TW>(Xm + tri_off(g.T, i) + (int64_t)(k0 - i) * TB, (int64_t)(g.T - i) * TB, TB,
+                                        R + (int64_t)t * TB * ldR + (int64_t)k0 * TB, ldR, TB,
+                                        (int64_t)(g.T - k0) * TB));
+            o.t1 = (int32_t)tw_terms.size();
+            outs_tw.push_back(o);
+          }
+        for (int pa = 0; pa < Ts; ++pa)
+          for (int pb = 0; pb < Ts; ++pb) {
+            GemmOut o = gemm_out(G0J + (int64_t)pa * TB * sp + (int64_t)pb * TB, sp, TB, TB, 0, (int)tw_terms.size());
+            if (g.tw > 0) {
+              o.c = G0W + (int64_t)pa * TB * sp + (int64_t)pb * TB;
+              o.ldc = sp;
+              o.beta = 1.0;
+            }
+            tw_terms.push_back(term<TW>(R + (int64_t)pa * TB * ldR + (int64_t)g.tw * TB, ldR, TB,
+                                        R + (int64_t)pb * TB * ldR + (int64_t)g.tw * TB, ldR, TB,
+                                        (int64_t)(g.T - g.tw) * TB));
+            o.t1 = (int32_t)tw_terms.size();
+            outs_tw.push_back(o);
+          }
+      }
+      c2b[c].o1 = (int64_t)outs_tw.size();
       // Phi = Gamma H, Xi = G0 H, Ups = H G0
       c3[c].o0 = (int64_t)outs_d.size();
       for (int64_t m = cbeg[c]; m < cbeg[c + 1]; ++m) {
@@ -715,10 +750,11 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, T
   // ---- window chunks
   for (int c = 0; c < nchunk; ++c) {
     solve_steps<TW>(runX[c], wininv, f, ldg, stat, st);
-    if (c2[c].o1 > c2[c].o0)
-      prof::timed(prof::GEMM, prof::on ? gemm_flops(tw_terms, outs_tw, c2[c].o0, c2[c].o1) : 0.0, st, [&] {
-        launch_tile_gemm<TW>(dtw_terms, douts_tw + c2[c].o0, (int)(c2[c].o1 - c2[c].o0), st);
-      });
+    for (const GemmBatch& b : {c2[c], c2b[c]})
+      if (b.o1 > b.o0)
+        prof::timed(prof::GEMM, prof::on ? gemm_flops(tw_terms, outs_tw, b.o0, b.o1) : 0.0, st, [&] {
+          launch_tile_gemm<TW>(dtw_terms, douts_tw + b.o0, (int)(b.o1 - b.o0), st);
+        });
     HIPCHK(hipGetLastError());
     gemm_d(c3[c]);
     gemm_d(c4[c]);
