@@ -412,18 +412,23 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     for (int64_t a = 0; a < M; ++a) {
       const int64_t c0 = f.bp[std::max<int64_t>(0, a - f.B)], r0 = f.bp[a], r1 = f.bp[a + 1], w = r1 - c0;
       for (int64_t p = r0; p < r1; ++p) bpl.brow[p] = off + (p - r0) * w - c0;
-      for (int64_t p0 = r0; p0 < r1; p0 += TB) {
-        const int nr = (int)std::min<int64_t>(TB, r1 - p0);
-        for (int64_t q0 = c0; q0 < r1 && q0 <= p0 + nr - 1; q0 += TB) {
-          BandItem it;
-          it.p0 = p0;
-          it.q0 = q0;
-          it.off = off + (p0 - r0) * w + (q0 - c0);
-          it.ld = w;
-          it.nr = nr;
-          it.nc = (int)std::min<int64_t>(TB, r1 - q0);
-          bpl.items.push_back(it);
-        }
+      // groups of 4 row tiles sweep the column tiles together, so the
+      // workgroups running at one time share their V rows in L2
+      for (int64_t g0 = r0; g0 < r1; g0 += 4 * TB) {
+        const int64_t g1 = std::min<int64_t>(r1, g0 + 4 * TB);
+        for (int64_t q0 = c0; q0 < g1; q0 += TB)
+          for (int64_t p0 = g0; p0 < g1; p0 += TB) {
+            const int nr = (int)std::min<int64_t>(TB, r1 - p0);
+            if (q0 > p0 + nr - 1) continue;  // right of the diagonal: never read
+            BandItem it;
+            it.p0 = p0;
+            it.q0 = q0;
+            it.off = off + (p0 - r0) * w + (q0 - c0);
+            it.ld = w;
+            it.nr = nr;
+            it.nc = (int)std::min<int64_t>(TB, r1 - q0);
+            bpl.items.push_back(it);
+          }
       }
       off += (r1 - r0) * w;
     }
