@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--no-lml", action="store_true", help="skip the separate LML-rate measurement")
     ap.add_argument("--no-grad", action="store_true", help="skip the LML+gradient measurement")
     ap.add_argument("--grad-evals", type=int, default=1, help="timed LML+gradient evaluations per precision")
+    ap.add_argument("--no-n131072", action="store_true",
+                    help="skip the LML+gradient rate at the n=131072 hyperparameter-fitting workload")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--small", action="store_true", help="n=65536 workload (quick check)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -235,6 +237,34 @@ def main():
                 "lml": abs(grad_res["mixed"]["lml"] - grad_res["fp64"]["lml"]) / abs(grad_res["fp64"]["lml"])}
             grad_res["mixed"]["speedup_vs_fp64"] = grad_res["fp64"]["s_per_eval"] / grad_res["mixed"]["s_per_eval"]
 
+    # LML + gradient evaluations per second at the n=131072 hyperparameter-fitting
+    # workload (d=8, M=128 blocks of 1024, B=2, |S|=512), at the generating
+    # hyperparameters and at the default start (l=1, sf2=Var y, sn2=0.1 Var y)
+    grad3 = None
+    if not args.no_grad and not args.no_n131072:
+        t0 = time.perf_counter()
+        p3 = synth.make_config(3)
+        log(f"n=131072 inputs drawn in {time.perf_counter() - t0:.1f} s")
+        X3, y3, S3 = dev(p3.X), dev(p3.y), dev(p3.S)
+        grad3 = {"workload": f"LML+gradient, n={p3.n}, d={p3.d}, M={p3.M}, B={p3.B}, |S|={p3.s}"}
+        thetas = {"generating": p3.log_hyp, "default_start": synth.default_theta0(p3.y, p3.d)}
+        for prec in [m for m in args.modes.split(",") if m]:
+            prob = lma.LmlProblem(X3, y3, p3.block_ptr, S3, p3.B, p3.prior_mean, precision=prec)
+            rec = {}
+            for name, th in thetas.items():
+                prob(th)  # warm-up (allocations, caches)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                k = 5
+                for _ in range(k):
+                    val, g = prob(th)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t1) / k
+                rec[name] = {"evals_per_s": 1.0 / dt, "s_per_eval": dt, "lml": val}
+            grad3[prec] = rec
+            log(f"n=131072 {prec} LML+grad: " + ", ".join(f"{k}: {v['s_per_eval'] * 1e3:.0f} ms" for k, v in rec.items()))
+        del X3, y3, S3
+
     f_fit, f_pred = algorithmic_flops(p)
     head = "fp64" if "fp64" in res else list(res)[0]
     prof = res[head]["profile"]
@@ -273,6 +303,7 @@ def main():
         "mixed": res.get("mixed"),
         "lml_evals_per_s_fp64": lml_rate,
         "lml_grad": grad_res or None,
+        "lml_grad_n131072": grad3,
         "alg_flops": {"fit": f_fit, "predict": f_pred},
         "roofline": roofline,
     }

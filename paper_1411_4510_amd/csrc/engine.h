@@ -125,8 +125,9 @@ void launch_band(const BandArgs<T>& a, hipStream_t st);
 
 // Host-side launchers (engine.hip).
 // mixed = true (float storage only): the covariance tile and the V_i V_j^T
-// correction are formed in float64 (float64 MFMA), the factor updates in
-// float32; the tile is rounded to float32 once, after the cancellation.
+// correction are formed in float64 (float64 MFMA), the factor updates as
+// float32 MFMA products whose sums are folded into float64 every 144 k; the
+// tile is rounded to float32 once, after the cancellation.
 template <typename T>
 void launch_update(const StepArgs<T>& a, bool mixed, hipStream_t st);
 template <typename T>

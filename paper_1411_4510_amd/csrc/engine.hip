@@ -37,9 +37,9 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
   if (a.j > kb) {
     const T* pa = ri.panel + (int64_t)(kb - ri.kbeg) * TB;
     const T* pb = rj.panel + (int64_t)(kb - rj.kbeg) * TB;
-    if constexpr (MIXED)
-      wave_gemm<T, T, true>(accl, pa, ri.ld, ri.nstore, pb, rj.ld, rj.nstore, 0, (a.j - kb) * TB, wr * 64, wc * 64,
-                            lane);
+    if constexpr (MIXED)  // float32 products, sums folded into the float64 accumulators
+      wave_gemm_fold(accl, pa, ri.ld, ri.nstore, pb, rj.ld, rj.nstore, 0, (a.j - kb) * TB, wr * 64, wc * 64, lane,
+                     accv);
     else
       wave_gemm<T, T>(accv, pa, ri.ld, ri.nstore, pb, rj.ld, rj.nstore, 0, (a.j - kb) * TB, wr * 64, wc * 64, lane);
   }
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
         if (row >= ri.nvalid || col >= rj.nvalid)
           val = (T)kv;  // padding: identity on the diagonal tile, zero elsewhere
         else if constexpr (MIXED)
-          val = (T)(kv - accv[rs][cs][v]) - accl[rs][cs][v];
+          val = (T)(kv - accv[rs][cs][v]);  // accl was folded into accv
         else
           val = (T)(kv - accv[rs][cs][v]);
         if (row < ri.nstore) out[(int64_t)row * ri.ld + col] = val;

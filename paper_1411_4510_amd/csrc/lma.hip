@@ -859,6 +859,21 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   HIPCHK(hipMemcpyAsync(&f.qsum, f.ptr<double>(f.o_q), 8, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   prof::flush();
+  if (const char* dump = std::getenv("LMA_DUMP_WINDOW")) {  // diagnostic: "m:path" writes window m's panel
+    const int64_t m = std::atoll(dump);
+    const char* path = std::strchr(dump, ':');
+    if (path && m >= 0 && m < M) {
+      const int64_t el = panel_elems(f.Tm[m], Ts + 1);
+      std::vector<char> h((size_t)(el * wsz));
+      HIPCHK(hipMemcpy(h.data(), f.ptr<char>(f.o_win) + f.win_off[m] * wsz, h.size(), hipMemcpyDeviceToHost));
+      if (FILE* fp = std::fopen(path + 1, "wb")) {
+        const int64_t hdr[4] = {f.Tm[m], f.twm[m], Ts, wsz};
+        std::fwrite(hdr, sizeof hdr, 1, fp);
+        std::fwrite(h.data(), 1, h.size(), fp);
+        std::fclose(fp);
+      }
+    }
+  }
   if (hstat[M]) {
     g_failed = -1;
     throw Err{LMA_E_NOT_PD, "Sigma_SS is not positive definite"};

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lma {
 
 typedef double dv4 __attribute__((ext_vector_type(4)));
@@ -67,11 +69,19 @@ __device__ inline int xcd_logical(int bid, int nb) {
 // never waits for the chunks in flight.
 // PERMA feeds the A rows of each 16-row sub-tile in the order r(4a+b) = a+4b, which
 // turns the float32 16x16 output layout into the float64 one (row l/16 + 4v).
-template <typename Tin, typename Tc, bool PERMA = false, int PF = 2>
-__device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
-                                          const Tin* __restrict__ A, int64_t lda, int anr,
-                                          const Tin* __restrict__ Bm, int64_t ldb, int bnr,
-                                          int k0, int k1, int arow0, int brow0, int lane) {
+// wave_gemm_fold (float32 accumulation, PERMA layout): every FOLD_ITERS steady
+// iterations (FOLD_ITERS*(PF+1)*16 k, 144 by default) the float32 accumulators are
+// added into the float64 ones and restarted from zero.  A single float32 chain over
+// the thousands of k of a late column step loses accuracy linearly in k (about 10x a
+// blocked float32 Cholesky at k ~ 3000); chains of 144 are more accurate than one.
+constexpr int FOLD_ITERS = 3;
+template <typename Tin, typename Tc, bool PERMA, int PF, bool FOLD>
+__device__ __forceinline__ void wave_gemm_impl(typename Mfma<Tc>::acc (&acc)[4][4],
+                                               const Tin* __restrict__ A, int64_t lda, int anr,
+                                               const Tin* __restrict__ Bm, int64_t ldb, int bnr,
+                                               int k0, int k1, int arow0, int brow0, int lane,
+                                               dv4 (&fold)[4][4]) {
+  static_assert(!FOLD || (PERMA && std::is_same<Tc, float>::value), "folding needs the float64 output layout");
   typedef typename V4<Tin>::type vin;
   const int r16 = lane & 15, kq = (lane >> 4) << 2;
   const Tin* pa[4];
@@ -107,16 +117,34 @@ __device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
       }                                                                                    \
     }                                                                                      \
   }
+#define LMA_FOLD()                                                                    \
+  if constexpr (FOLD) {                                                              \
+    _Pragma("unroll") for (int a_ = 0; a_ < 4; ++a_) {                               \
+      _Pragma("unroll") for (int b_ = 0; b_ < 4; ++b_) {                             \
+        _Pragma("unroll") for (int v_ = 0; v_ < 4; ++v_) {                           \
+          fold[a_][b_][v_] += (double)acc[a_][b_][v_];                               \
+          acc[a_][b_][v_] = Tc(0);                                                   \
+        }                                                                            \
+      }                                                                              \
+    }                                                                                \
+  }
 #pragma unroll
   for (int p = 0; p < PF; ++p)
     if (p < nc) LMA_LOAD_CHUNK(p, p)
   int c = 0;
+  int since_fold = 0;
   // steady state: every prefetch is in range, no branches in the body
   for (; c + 2 * PF < nc; c += PF + 1) {
 #pragma unroll
     for (int q = 0; q <= PF; ++q) {
       LMA_LOAD_CHUNK(c + q + PF, (q + PF) % (PF + 1))
       LMA_MMA_SLOT(q)
+    }
+    if constexpr (FOLD) {
+      if (++since_fold == FOLD_ITERS) {
+        since_fold = 0;
+        LMA_FOLD()
+      }
     }
   }
   // tail: at most 2*PF+1 chunks, slots known at compile time
@@ -127,8 +155,27 @@ __device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
       LMA_MMA_SLOT(t % (PF + 1))
     }
   }
+  LMA_FOLD()
 #undef LMA_LOAD_CHUNK
 #undef LMA_MMA_SLOT
+#undef LMA_FOLD
+}
+
+template <typename Tin, typename Tc, bool PERMA = false, int PF = 2>
+__device__ __forceinline__ void wave_gemm(typename Mfma<Tc>::acc (&acc)[4][4],
+                                          const Tin* __restrict__ A, int64_t lda, int anr,
+                                          const Tin* __restrict__ Bm, int64_t ldb, int bnr,
+                                          int k0, int k1, int arow0, int brow0, int lane) {
+  dv4 unused[4][4];
+  wave_gemm_impl<Tin, Tc, PERMA, PF, false>(acc, A, lda, anr, Bm, ldb, bnr, k0, k1, arow0, brow0, lane, unused);
+}
+
+// float32 products (PERMA layout) with the sums folded into the float64 accumulators fold
+template <int PF = 2>
+__device__ __forceinline__ void wave_gemm_fold(fv4 (&acc)[4][4], const float* __restrict__ A, int64_t lda, int anr,
+                                               const float* __restrict__ Bm, int64_t ldb, int bnr, int k0, int k1,
+                                               int arow0, int brow0, int lane, dv4 (&fold)[4][4]) {
+  wave_gemm_impl<float, float, true, PF, true>(acc, A, lda, anr, Bm, ldb, bnr, k0, k1, arow0, brow0, lane, fold);
 }
 
 template <typename Tc>
