@@ -276,6 +276,27 @@ def cmd_evaluate(a):
             json.dump({"summary": s, "sets": rows}, f)
 
 
+def cmd_merge_eval(a):
+    """Merge evaluation outputs (disjoint set ranges) into the parameters' record."""
+    rows, cap = [], None
+    for path in a.inputs:
+        with open(path) as f:
+            e = json.load(f)
+        rows += e["sets"]
+        cap = e["summary"]["step_cap"]
+    rows.sort(key=lambda r: r["index"])
+    idx = [r["index"] for r in rows]
+    if len(set(idx)) != len(idx):
+        raise SystemExit("overlapping evaluation sets")
+    with open(a.record) as f:
+        rec = json.load(f)
+    rec["evaluation"] = summarise(rows, cap)
+    rec["evaluation_sets"] = rows
+    with open(a.record, "w") as f:
+        json.dump(rec, f, indent=1)
+    log(json.dumps(rec["evaluation"]))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -302,8 +323,11 @@ def main(argv=None):
     p3.add_argument("--count", type=int, default=100)
     p3.add_argument("--steps", type=int, default=150)
     p3.add_argument("--out", default=None)
+    p4 = sub.add_parser("merge-eval")
+    p4.add_argument("--inputs", nargs="+", required=True)
+    p4.add_argument("--record", required=True)
     a = ap.parse_args(argv)
-    {"labels": cmd_labels, "train": cmd_train, "evaluate": cmd_evaluate}[a.cmd](a)
+    {"labels": cmd_labels, "train": cmd_train, "evaluate": cmd_evaluate, "merge-eval": cmd_merge_eval}[a.cmd](a)
 
 
 if __name__ == "__main__":
