@@ -71,7 +71,10 @@ typedef struct {
   double prior_mean;          /* constant prior mean mu */
   int32_t precision;          /* lma_precision */
   int32_t reserved;           /* must be 0 */
-  int64_t mem_budget_bytes;   /* 0 = no limit; otherwise the state may not exceed it (LMA_E_NOMEM) */
+  int64_t mem_budget_bytes;   /* 0 = no limit.  Otherwise the state stays within it: when every
+                                 window's factor does not fit, the windows are processed in chunks
+                                 and refactored by each pass that needs them (lma_state_chunks);
+                                 LMA_E_NOMEM when not even one window fits */
 } lma_problem;
 
 /* Opaque fit state, owned by the library (release with lma_free).  Holds the
@@ -126,6 +129,15 @@ void lma_release_cache(void);
 
 /* LML of a fitted state (host scalar) without recomputation. */
 lma_status lma_state_lml(const lma_state *f, double *lml);
+
+/* Device bytes a fitted state holds, and the number of chunks its window
+ * factors are processed in: 1 when every window's factor is resident; more
+ * when mem_budget_bytes was too small for that, in which case the state holds
+ * one chunk of windows at a time and lma_predict / lma_lml refactor the
+ * windows chunk by chunk (same arithmetic as the fit).  Both return -1 for a
+ * NULL state. */
+int64_t lma_state_bytes(const lma_state *f);
+int64_t lma_state_chunks(const lma_state *f);
 
 /* Message for the last error on the calling thread ("" if none). */
 const char *lma_last_error(void);

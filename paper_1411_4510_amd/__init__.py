@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "liblma.so")
 
 LMA_OK, LMA_E_ARG, LMA_E_NOT_PD, LMA_E_HIP, LMA_E_NOMEM = 0, 1, 2, 3, 4
 PRECISION = {"fp64": 0, "mixed": 1}
-EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml",
+EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml", "lma_state_bytes", "lma_state_chunks",
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
            "lma_profile_read", "lma_release_cache")
 DS_EXPORTS = ("lma_ds_create", "lma_ds_free", "lma_ds_set_params", "lma_ds_get_params", "lma_ds_features",
@@ -91,6 +91,9 @@ def load(path: str = LIB_PATH):
     lib.lma_free.restype = None
     lib.lma_state_lml.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     lib.lma_state_lml.restype = st
+    for name in ("lma_state_bytes", "lma_state_chunks"):
+        getattr(lib, name).argtypes = [vp]
+        getattr(lib, name).restype = ctypes.c_int64
     lib.lma_last_error.restype = ctypes.c_char_p
     lib.lma_failed_block.restype = i64
     lib.lma_version.restype = ctypes.c_char_p
@@ -193,6 +196,14 @@ class State:
         out = ctypes.c_double()
         _check(_lib.lma_state_lml(self._h, ctypes.byref(out)))
         return out.value
+
+    def nbytes(self):
+        """Device bytes the state holds."""
+        return int(_lib.lma_state_bytes(self._h))
+
+    def chunks(self):
+        """Window chunks (1: every window's factor is resident)."""
+        return int(_lib.lma_state_chunks(self._h))
 
     def free(self):
         if self._h:

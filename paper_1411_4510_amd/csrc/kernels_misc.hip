@@ -184,6 +184,7 @@ __global__ __launch_bounds__(256) void k_pred_xi(XiArgs<T> a) {
   double acc = 0.0;
   for (int dl = 0; dl <= a.B && dl <= q; ++dl) {
     const int m = q - dl;
+    if (m < a.m0 || m >= a.m1) continue;
     const int64_t ldx = (int64_t)a.Tm[m] * 128;
     const T* row = a.Xbuf + a.Xoff[m] + (u - a.uptr[m]) * ldx;
     const int k0 = dl == 0 ? 0 : a.twm[m] * 128;
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void k_pred_xi(XiArgs<T> a) {
     }
   }
   for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-  if (lane == 0) a.xi[u] = acc;
+  if (lane == 0) a.xi[u] = a.accumulate ? a.xi[u] + acc : acc;
 }
 
 // var_u = sigma_s^2 + sigma_n^2 - |V_u|^2 - xi_u + |L_ddot^-1 E_u|^2.

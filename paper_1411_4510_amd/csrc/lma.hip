@@ -238,9 +238,9 @@ void set_err(const Err& e) {
 // ---------------------------------------------------------------------------
 template <typename TW>
 void build_window_run(lma_state& f, Run<TW>& run, TW* winbase, const double* Xs, const double* Vt, const TW* c,
-                      const double* Ss, bool band) {
+                      const double* Ss, bool band, int64_t m0, int64_t m1) {
   const int Ts = (int)f.Ts;
-  for (int64_t m = 0; m < f.M; ++m) {
+  for (int64_t m = m0; m < m1; ++m) {
     const WinGeom g = win_geom(f.bp, f.M, f.B, m);
     TW* base = winbase + f.win_off[m];
     run.add_problem(g.T, Ts + 1, g.tw, false, (int)m);
@@ -318,6 +318,39 @@ struct BandPlan {
   }
 };
 
+// Summary terms of the windows [m0, m1) into group 0, added to what earlier
+// chunks left there (chunk order fixes the summation order).
+template <typename TW>
+void build_summary_chunk(lma_state& f, std::vector<GemmTerm<TW>>& terms, TW* winbase, int64_t m0, int64_t m1,
+                         bool accumulate) {
+  const int nt = (int)f.Ts + 1;
+  f.ntile = nt * (nt + 1) / 2;
+  f.groups = 1;
+  double* partial = f.ptr<double>(f.o_partial);
+  for (int ta = 0; ta < nt; ++ta)
+    for (int tb = 0; tb <= ta; ++tb) {
+      const int t = ta * (ta + 1) / 2 + tb;
+      GemmOut o = gemm_out(partial + (int64_t)t * TB * TB, TB, TB, TB, accumulate ? 1 : 0, (int)terms.size());
+      for (int64_t m = m0; m < m1; ++m) {
+        const WinGeom g = win_geom(f.bp, f.M, f.B, m);
+        TW* rhs = winbase + f.win_off[m] + jpanel_off(g.T);
+        const int64_t ld = (int64_t)g.T * TB;
+        GemmTerm<TW> tm;
+        tm.a = rhs + (int64_t)ta * TB * ld;
+        tm.lda = ld;
+        tm.anr = TB;
+        tm.b = rhs + (int64_t)tb * TB * ld;
+        tm.ldb = ld;
+        tm.bnr = TB;
+        tm.k0 = g.tw * TB;
+        tm.k1 = g.T * TB;
+        terms.push_back(tm);
+      }
+      o.t1 = (int32_t)terms.size();
+      f.sumout.push_back(o);
+    }
+}
+
 lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool keep) {
   check_problem(p);
   ensure_init();
@@ -342,64 +375,93 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   const int Ts = (int)f.Ts;
   const int64_t wsz = mixed ? 4 : 8;
 
-  // ---- geometry and memory plan
-  Arena& ar = f.ar;
-  f.o_Xs64 = ar.reserve(8 * n * d);
-  f.o_Ss64 = ar.reserve(8 * s * d);
-  f.o_c64 = ar.reserve(8 * n);
-  if (mixed) {
-    f.o_c32 = ar.reserve(4 * n);
-  }
-  f.o_Vt64 = ar.reserve(8 * n * sp);
-  f.o_Lss = ar.reserve(8 * panel_elems(Ts, 0));
-  f.o_Lss_inv = ar.reserve(8 * (int64_t)Ts * TB * TB);
+  // ---- window geometry
   f.Tm.resize(M);
   f.twm.resize(M);
   f.win_off.resize(M);
-  int64_t win_elems = 0, inv_elems = 0;
+  f.inv_off.resize(M);
+  std::vector<int64_t> wel(M), iel(M);
   int maxT = 0;
   for (int64_t m = 0; m < M; ++m) {
     const WinGeom g = win_geom(f.bp, M, f.B, m);
     f.Tm[m] = g.T;
     f.twm[m] = g.tw;
-    f.win_off[m] = win_elems;
-    win_elems += panel_elems(g.T, Ts + 1);
-    inv_elems += (int64_t)g.T * TB * TB;
+    wel[m] = panel_elems(g.T, Ts + 1);
+    iel[m] = (int64_t)g.T * TB * TB;
     maxT = std::max(maxT, g.T);
   }
-  f.o_win = ar.reserve(wsz * win_elems);
-  f.o_win_inv = ar.reserve(wsz * inv_elems);
-  {
-    const int nt = Ts + 1, ntile = nt * (nt + 1) / 2;
-    int groups = (int)std::max<int64_t>(1, std::min<int64_t>(M, cdiv(1024, ntile)));
-    groups = (int)cdiv(M, cdiv(M, groups));
-    f.o_partial = ar.reserve(8 * (int64_t)groups * ntile * TB * TB);
-  }
-  f.o_Sdd = ar.reserve(8 * sp * sp);
-  f.o_ydd = ar.reserve(8 * sp);
-  f.o_q = ar.reserve(8);
-  f.o_Ldd = ar.reserve(8 * panel_elems(Ts, 0));
-  f.o_Ldd_inv = ar.reserve(8 * (int64_t)Ts * TB * TB);
-  f.o_g = ar.reserve(8 * sp);
-  f.n_logdiag = (int64_t)(M + 2) * std::max(maxT, Ts);
-  f.o_logdiag = ar.reserve(8 * f.n_logdiag);
-  f.n_status = M + 2;
-  f.o_status = ar.reserve(4 * f.n_status);
   f.vec_elems = 0;
   for (int64_t m = 0; m < M; ++m) f.vec_elems += (int64_t)f.Tm[m] * TB;
-  f.o_wt = ar.reserve(8 * 10 * M);
-  f.o_xJ = ar.reserve(8 * f.vec_elems);
-  f.o_xW = ar.reserve(8 * f.vec_elems);
-  f.o_tJ = ar.reserve(8 * f.vec_elems);
-  f.o_tW = ar.reserve(8 * f.vec_elems);
-  f.o_hJ = ar.reserve(8 * M * sp);
-  f.o_hW = ar.reserve(8 * M * sp);
-  if (mixed) {
-    f.o_cg = ar.reserve(8 * n);
-    f.o_dg = ar.reserve(8 * sp);
-    f.o_tvec = ar.reserve(8 * sp);
-    f.o_rho = ar.reserve(8 * sp);
-  }
+  // Chunks of consecutive windows whose factors (panels and inverted diagonal
+  // tiles) fit in area_cap bytes; area_cap <= 0 puts all windows in one chunk.
+  auto set_chunks = [&](int64_t area_cap) -> bool {
+    f.chunk.assign(1, 0);
+    int64_t wacc = 0, iacc = 0;
+    f.win_area = f.inv_area = 0;
+    for (int64_t m = 0; m < M; ++m) {
+      const int64_t need = wsz * (wel[m] + iel[m]);
+      if (area_cap > 0 && need > area_cap) return false;
+      if (area_cap > 0 && m > f.chunk.back() && wsz * (wacc + iacc) + need > area_cap) {
+        f.chunk.push_back(m);
+        wacc = iacc = 0;
+      }
+      f.win_off[m] = wacc;
+      f.inv_off[m] = iacc;
+      wacc += wel[m];
+      iacc += iel[m];
+      f.win_area = std::max(f.win_area, wacc);
+      f.inv_area = std::max(f.inv_area, iacc);
+    }
+    f.chunk.push_back(M);
+    return true;
+  };
+  set_chunks(0);
+
+  // ---- memory plan (redone below with chunks when mem_budget_bytes requires)
+  Arena& ar = f.ar;
+  auto plan_fixed = [&]() {
+    ar = Arena();
+    f.o_Xs64 = ar.reserve(8 * n * d);
+    f.o_Ss64 = ar.reserve(8 * s * d);
+    f.o_c64 = ar.reserve(8 * n);
+    if (mixed) f.o_c32 = ar.reserve(4 * n);
+    f.o_Vt64 = ar.reserve(8 * n * sp);
+    f.o_Lss = ar.reserve(8 * panel_elems(Ts, 0));
+    f.o_Lss_inv = ar.reserve(8 * (int64_t)Ts * TB * TB);
+    f.o_win = ar.reserve(wsz * f.win_area);
+    f.o_win_inv = ar.reserve(wsz * f.inv_area);
+    {
+      const int nt = Ts + 1, ntile = nt * (nt + 1) / 2;
+      int groups = (int)std::max<int64_t>(1, std::min<int64_t>(M, cdiv(1024, ntile)));
+      groups = (int)cdiv(M, cdiv(M, groups));
+      if (f.streaming()) groups = 1;
+      f.o_partial = ar.reserve(8 * (int64_t)groups * ntile * TB * TB);
+    }
+    f.o_Sdd = ar.reserve(8 * sp * sp);
+    f.o_ydd = ar.reserve(8 * sp);
+    f.o_q = ar.reserve(8);
+    f.o_Ldd = ar.reserve(8 * panel_elems(Ts, 0));
+    f.o_Ldd_inv = ar.reserve(8 * (int64_t)Ts * TB * TB);
+    f.o_g = ar.reserve(8 * sp);
+    f.n_logdiag = (int64_t)(M + 2) * std::max(maxT, Ts);
+    f.o_logdiag = ar.reserve(8 * f.n_logdiag);
+    f.n_status = M + 2;
+    f.o_status = ar.reserve(4 * f.n_status);
+    f.o_wt = ar.reserve(8 * 10 * M);
+    f.o_xJ = ar.reserve(8 * f.vec_elems);
+    f.o_xW = ar.reserve(8 * f.vec_elems);
+    f.o_tJ = ar.reserve(8 * f.vec_elems);
+    f.o_tW = ar.reserve(8 * f.vec_elems);
+    f.o_hJ = ar.reserve(8 * M * sp);
+    f.o_hW = ar.reserve(8 * M * sp);
+    if (mixed) {
+      f.o_cg = ar.reserve(8 * n);
+      f.o_dg = ar.reserve(8 * sp);
+      f.o_tvec = ar.reserve(8 * sp);
+      f.o_rho = ar.reserve(8 * sp);
+    }
+  };
+  plan_fixed();
 
   // ---- residual band (overlapping windows only): panel of block a spans the
   // points of blocks max(0, a-B) .. a; tiles entirely right of the diagonal
@@ -442,9 +504,10 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
   auto build_runs = [&](char* base) {
     f.ar.base = base;
     f.runS = Run<double>();
-    f.runW32 = Run<float>();
-    f.runW64 = Run<double>();
     f.runD = Run<double>();
+    const int nch = (int)f.chunk.size() - 1;
+    f.runsW32.assign(mixed ? nch : 0, Run<float>());
+    f.runsW64.assign(mixed ? 0 : nch, Run<double>());
     // S run: Sigma_SS with the training rows as right-hand sides
     const int Rn = (int)cdiv(n, TB);
     f.runS.add_problem(Ts, Rn, 0, false, -1);
@@ -456,18 +519,32 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
                                             SRC_KERNEL, 0));
     }
     f.runS.schedule();
-    // window run
-    if (mixed) {
-      build_window_run<float>(f, f.runW32, f.ptr<float>(f.o_win), f.ptr<double>(f.o_Xs64), f.ptr<double>(f.o_Vt64),
-                              f.ptr<float>(f.o_c32), f.ptr<double>(f.o_Ss64), use_band);
-      f.runW32.schedule();
-      build_summary<float>(f, f.sum32, f.ptr<float>(f.o_win));
-    } else {
-      build_window_run<double>(f, f.runW64, f.ptr<double>(f.o_win), f.ptr<double>(f.o_Xs64),
-                               f.ptr<double>(f.o_Vt64), f.ptr<double>(f.o_c64), f.ptr<double>(f.o_Ss64), use_band);
-      f.runW64.schedule();
-      build_summary<double>(f, f.sum64, f.ptr<double>(f.o_win));
-    }
+    // window runs (one per chunk) and the summary products
+    auto window_runs = [&](auto& runs, auto& sums, auto* winbase, auto* cvec) {
+      using TW = typename std::remove_const<typename std::remove_pointer<decltype(winbase)>::type>::type;
+      for (int c = 0; c < nch; ++c) {
+        build_window_run<TW>(f, runs[c], winbase, f.ptr<double>(f.o_Xs64), f.ptr<double>(f.o_Vt64), cvec,
+                             f.ptr<double>(f.o_Ss64), use_band, f.chunk[c], f.chunk[c + 1]);
+        runs[c].schedule();
+      }
+      f.sumsplit.assign(1, 0);
+      if (nch == 1) {
+        build_summary<TW>(f, sums, winbase);
+      } else {
+        f.sumout.clear();
+        sums.clear();
+        for (int c = 0; c < nch; ++c) {
+          build_summary_chunk<TW>(f, sums, winbase, f.chunk[c], f.chunk[c + 1], c > 0);
+          f.sumsplit.push_back((int64_t)f.sumout.size());
+        }
+        f.sumsplit.pop_back();
+      }
+      f.sumsplit.push_back((int64_t)f.sumout.size());
+    };
+    if (mixed)
+      window_runs(f.runsW32, f.sum32, f.ptr<float>(f.o_win), f.ptr<float>(f.o_c32));
+    else
+      window_runs(f.runsW64, f.sum64, f.ptr<double>(f.o_win), f.ptr<double>(f.o_c64));
     // Sigma_ddot run (explicit matrix, no right-hand sides)
     f.runD.add_problem(Ts, 0, 0, false, -2);
     for (int i = 0; i < Ts; ++i) {
@@ -496,7 +573,9 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
         f.kvcg.push_back(it);
       }
       int64_t vo = 0;
+      f.kmvsplit.assign(M + 1, 0);
       for (int64_t m = 0; m < M; ++m) {
+        f.kmvsplit[m] = (int64_t)f.kvkmv.size();
         const WinGeom g = win_geom(f.bp, M, f.B, m);
         const int c0 = (int)f.kvcols.size();
         kv_window_cols(f.kvcols, g, Xs, d, f.ptr<double>(f.o_xJ) + vo, f.ptr<double>(f.o_xW) + vo);
@@ -518,26 +597,53 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
         }
         vo += (int64_t)g.T * TB;
       }
+      f.kmvsplit[M] = (int64_t)f.kvkmv.size();
     }
   };
-  build_runs(nullptr);
-  const int64_t meta = f.runS.meta_bytes() + (mixed ? f.runW32.meta_bytes() : f.runW64.meta_bytes()) +
-                       f.runD.meta_bytes();
-  f.o_kvcols = ar.reserve(sizeof(KvCol) * std::max<size_t>(f.kvcols.size(), 1));
-  f.o_kvcg = ar.reserve(sizeof(KvItem) * std::max<size_t>(f.kvcg.size(), 1));
-  f.o_kvkmv = ar.reserve(sizeof(KvItem) * std::max<size_t>(f.kvkmv.size(), 1));
-  const int64_t sterm_bytes = mixed ? sizeof(GemmTerm<float>) * f.sum32.size() : sizeof(GemmTerm<double>) * f.sum64.size();
-  f.o_meta = ar.reserve(meta);
-  f.o_sumterms = ar.reserve(sterm_bytes);
-  f.o_sumout = ar.reserve(sizeof(GemmOut) * f.sumout.size());
-  f.ar.cap = f.ar.used;
-  if (use_band && p->mem_budget_bytes > 0 && f.ar.cap + bpl.bytes > p->mem_budget_bytes) use_band = false;
-  if (p->mem_budget_bytes > 0 && f.ar.cap > p->mem_budget_bytes) {
-    char buf[160];
-    snprintf(buf, sizeof buf, "state needs %lld bytes, over the budget of %lld", (long long)f.ar.cap,
-             (long long)p->mem_budget_bytes);
-    throw Err{LMA_E_NOMEM, buf};
+  auto runs_meta = [&]() {
+    int64_t b = f.runS.meta_bytes() + f.runD.meta_bytes();
+    for (auto& r : f.runsW32) b += r.meta_bytes();
+    for (auto& r : f.runsW64) b += r.meta_bytes();
+    return b;
+  };
+  int64_t meta = 0, sterm_bytes = 0;
+  auto plan_meta = [&]() {
+    build_runs(nullptr);
+    meta = runs_meta();
+    f.o_kvcols = ar.reserve(sizeof(KvCol) * std::max<size_t>(f.kvcols.size(), 1));
+    f.o_kvcg = ar.reserve(sizeof(KvItem) * std::max<size_t>(f.kvcg.size(), 1));
+    f.o_kvkmv = ar.reserve(sizeof(KvItem) * std::max<size_t>(f.kvkmv.size(), 1));
+    sterm_bytes = mixed ? sizeof(GemmTerm<float>) * f.sum32.size() : sizeof(GemmTerm<double>) * f.sum64.size();
+    f.o_meta = ar.reserve(meta);
+    f.o_sumterms = ar.reserve(sterm_bytes);
+    f.o_sumout = ar.reserve(sizeof(GemmOut) * f.sumout.size());
+    f.ar.cap = f.ar.used;
+  };
+  plan_meta();
+  const int64_t budget = p->mem_budget_bytes;
+  if (budget > 0 && f.ar.cap > budget) {
+    // Too small for every window's factors: keep one chunk of windows at a time.
+    use_band = false;
+    int64_t avail = budget - (f.ar.cap - wsz * (f.win_area + f.inv_area));
+    bool ok = false;
+    for (int attempt = 0; attempt < 4 && avail > 0; ++attempt) {
+      if (!set_chunks(avail)) break;
+      plan_fixed();
+      plan_meta();
+      if (f.ar.cap <= budget) {
+        ok = true;
+        break;
+      }
+      avail -= f.ar.cap - budget;
+    }
+    if (!ok) {
+      char buf[200];
+      snprintf(buf, sizeof buf, "mem_budget_bytes %lld is too small even for one window's factors at a time",
+               (long long)budget);
+      throw Err{LMA_E_NOMEM, buf};
+    }
   }
+  if (use_band && budget > 0 && f.ar.cap + bpl.bytes > budget) use_band = false;
   {
     void* mem = devcache::get((size_t)f.ar.cap);
     if (!mem) {
@@ -558,12 +664,13 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     char* mp = f.ptr<char>(f.o_meta);
     f.runS.upload(mp, st);
     mp += f.runS.meta_bytes();
-    if (mixed) {
-      f.runW32.upload(mp, st);
-      mp += f.runW32.meta_bytes();
-    } else {
-      f.runW64.upload(mp, st);
-      mp += f.runW64.meta_bytes();
+    for (auto& r : f.runsW32) {
+      r.upload(mp, st);
+      mp += r.meta_bytes();
+    }
+    for (auto& r : f.runsW64) {
+      r.upload(mp, st);
+      mp += r.meta_bytes();
     }
     f.runD.upload(mp, st);
     if (use_band) {
@@ -660,14 +767,30 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     else
       band_launch(static_cast<double*>(bpl.mem));
   }
-  if (mixed) {
-    run_with_stride(f.runW32, f.ptr<float>(f.o_win_inv), 0, (int)sp, use_band);
-    prof::timed(prof::GEMM, prof::on ? gemm_flops(f.sum32, f.sumout, 0, (int64_t)f.sumout.size()) : 0.0, st, [&] { launch_tile_gemm<float>(reinterpret_cast<const GemmTerm<float>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
-  } else {
-    run_with_stride(f.runW64, f.ptr<double>(f.o_win_inv), 0, (int)sp, use_band);
-    prof::timed(prof::GEMM, prof::on ? gemm_flops(f.sum64, f.sumout, 0, (int64_t)f.sumout.size()) : 0.0, st, [&] { launch_tile_gemm<double>(reinterpret_cast<const GemmTerm<double>*>(f.ptr<char>(f.o_sumterms)), reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)), (int)f.sumout.size(), st); });
+  const int nch = (int)f.chunk.size() - 1;
+  // factor the windows of chunk c (their panels and inverses in the window area)
+  auto factor_chunk = [&](int c) {
+    if (mixed)
+      run_with_stride(f.runsW32[c], f.ptr<float>(f.o_win_inv), (int)f.chunk[c], (int)sp, use_band);
+    else
+      run_with_stride(f.runsW64[c], f.ptr<double>(f.o_win_inv), (int)f.chunk[c], (int)sp, use_band);
+  };
+  for (int c = 0; c < nch; ++c) {
+    factor_chunk(c);
+    const int64_t o0 = f.sumsplit[c], o1 = f.sumsplit[c + 1];
+    const GemmOut* douts = reinterpret_cast<const GemmOut*>(f.ptr<char>(f.o_sumout)) + o0;
+    if (mixed)
+      prof::timed(prof::GEMM, prof::on ? gemm_flops(f.sum32, f.sumout, o0, o1) : 0.0, st, [&] {
+        launch_tile_gemm<float>(reinterpret_cast<const GemmTerm<float>*>(f.ptr<char>(f.o_sumterms)), douts,
+                                (int)(o1 - o0), st);
+      });
+    else
+      prof::timed(prof::GEMM, prof::on ? gemm_flops(f.sum64, f.sumout, o0, o1) : 0.0, st, [&] {
+        launch_tile_gemm<double>(reinterpret_cast<const GemmTerm<double>*>(f.ptr<char>(f.o_sumterms)), douts,
+                                 (int)(o1 - o0), st);
+      });
+    HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipGetLastError());
   {
     SummaryArgs sa;
     sa.partial = f.ptr<double>(f.o_partial);
@@ -712,7 +835,7 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     int64_t* t_rhs = t_vec + M;
     int32_t* t_T = reinterpret_cast<int32_t*>(t_rhs + M);
     int32_t* t_tw = t_T + M;
-    int64_t inv_acc = 0, vec_acc = 0;
+    int64_t vec_acc = 0;
     int maxTw = 0;
     for (int64_t m = 0; m < M; ++m) {
       const WinGeom g = win_geom(f.bp, M, f.B, m);
@@ -721,12 +844,11 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       t_dstart[m] = g.dstart;
       t_dlen[m] = g.b;
       t_panel[m] = f.win_off[m];
-      t_inv[m] = inv_acc;
+      t_inv[m] = f.inv_off[m];
       t_vec[m] = vec_acc;
       t_rhs[m] = f.win_off[m] + jpanel_off(g.T);
       t_T[m] = g.T;
       t_tw[m] = g.tw;
-      inv_acc += (int64_t)g.T * TB * TB;
       vec_acc += (int64_t)g.T * TB;
       maxTw = std::max(maxTw, g.T);
     }
@@ -758,10 +880,35 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
     ha.hW = f.ptr<double>(f.o_hW);
     ha.sp = (int)sp;
     ha.M = (int)M;
-    auto winvec = [&](auto* panels, auto* invs, double* vJ, double* vW) {
+    // chunk c's windows m0..m1-1 seen by the kernels as windows 0..m1-m0-1
+    auto sub = [&](int c) {
+      const int64_t m0 = f.chunk[c];
+      WinTab w = f.wt;
+      w.wstart += m0;
+      w.wlen += m0;
+      w.dstart += m0;
+      w.dlen += m0;
+      w.panel += m0;
+      w.inv += m0;
+      w.vec += m0;
+      w.rhs += m0;
+      w.T += m0;
+      w.tw += m0;
+      return w;
+    };
+    auto nwin = [&](int c) { return (int)(f.chunk[c + 1] - f.chunk[c]); };
+    auto h_chunk = [&](int c) {
+      HArgs hc = ha;
+      hc.w = sub(c);
+      hc.M = nwin(c);
+      hc.hJ = ha.hJ + f.chunk[c] * sp;
+      hc.hW = ha.hW + f.chunk[c] * sp;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(hc, st); });
+    };
+    auto winvec = [&](auto* panels, auto* invs, double* vJ, double* vW, int c) {
       using TT = typename std::remove_const<typename std::remove_pointer<decltype(panels)>::type>::type;
       WinVecArgs<TT> va;
-      va.w = f.wt;
+      va.w = sub(c);
       va.panels = panels;
       va.invs = invs;
       va.sp = (int)sp;
@@ -772,23 +919,35 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       return va;
     };
     // beta from the whitened right-hand sides (forward half) and a backward solve
-    auto beta_solve = [&](auto* panels, auto* invs) {
-      auto va = winvec(panels, invs, xJ, xW);
+    auto beta_solve = [&](auto* panels, auto* invs, int c) {
+      auto va = winvec(panels, invs, xJ, xW, c);
       using TT = typename std::remove_const<typename std::remove_pointer<decltype(panels)>::type>::type;
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_ycp<TT>(va, (int)M, maxTw, st); });
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_bwd<TT>(va, (int)M, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_ycp<TT>(va, nwin(c), maxTw, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_bwd<TT>(va, nwin(c), st); });
       HIPCHK(hipGetLastError());
     };
-    auto full_solve = [&](auto* panels, auto* invs, double* vJ, double* vW) {
-      auto va = winvec(panels, invs, vJ, vW);
+    auto full_solve = [&](auto* panels, auto* invs, double* vJ, double* vW, int c) {
+      auto va = winvec(panels, invs, vJ, vW, c);
       using TT = typename std::remove_const<typename std::remove_pointer<decltype(panels)>::type>::type;
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_fwd<TT>(va, (int)M, maxTw, st); });
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_bwd<TT>(va, (int)M, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_fwd<TT>(va, nwin(c), maxTw, st); });
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_bwd<TT>(va, nwin(c), st); });
       HIPCHK(hipGetLastError());
+    };
+    // x += alpha t over the vector entries of chunk c's windows
+    auto axpy_chunk = [&](double alpha, int c) {
+      const int64_t v0 = t_vec[f.chunk[c]], v1 = f.chunk[c + 1] < M ? t_vec[f.chunk[c + 1]] : f.vec_elems;
+      prof::timed(prof::OTHER, 0.0, st, [&] { launch_axpy2(xJ + v0, xW + v0, tJ + v0, tW + v0, alpha, v1 - v0, st); });
+    };
+    // the factors of chunk c are resident: with several chunks, factor them again
+    auto resident = [&](int c) {
+      if (nch > 1) factor_chunk(c);
     };
     if (!mixed) {
-      beta_solve(f.ptr<double>(f.o_win), f.ptr<double>(f.o_win_inv));
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+      for (int c = 0; c < nch; ++c) {
+        resident(c);
+        beta_solve(f.ptr<double>(f.o_win), f.ptr<double>(f.o_win_inv), c);
+        h_chunk(c);
+      }
       HIPCHK(hipGetLastError());
     } else {
       const float* P = f.ptr<float>(f.o_win);
@@ -796,10 +955,6 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       double* cg = f.ptr<double>(f.o_cg);
       double* dg = f.ptr<double>(f.o_dg);
       double* tvec = f.ptr<double>(f.o_tvec);
-      // 1. beta0 with the float32 factors
-      beta_solve(P, I);
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
-      // 2. one refinement of beta against the float64 residual covariance
       KvArgs kv;
       kv.cols = reinterpret_cast<const KvCol*>(f.ptr<char>(f.o_kvcols));
       kv.d = (int)d;
@@ -807,17 +962,25 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       kv.sf2 = f.sf2;
       kv.sn2 = f.sn2;
       kv.mu = 0.0;
+      // c' = c - K_XS g over all training points
       kv.items = reinterpret_cast<const KvItem*>(f.ptr<char>(f.o_kvcg));
       kv.nitems = (int32_t)f.kvcg.size();
       kv.mode = KV_CG;
       prof::timed(prof::OTHER, 0.0, st, [&] { launch_kvec(kv, st); });
-      kv.items = reinterpret_cast<const KvItem*>(f.ptr<char>(f.o_kvkmv));
-      kv.nitems = (int32_t)f.kvkmv.size();
-      kv.mode = KV_KMV;
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_kvec(kv, st); });
-      full_solve(P, I, tJ, tW);
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_axpy2(xJ, xW, tJ, tW, 1.0, f.vec_elems, st); });
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+      for (int c = 0; c < nch; ++c) {
+        resident(c);
+        // 1. beta0 with the float32 factors
+        beta_solve(P, I, c);
+        h_chunk(c);
+        // 2. one refinement of beta against the float64 residual covariance
+        kv.items = reinterpret_cast<const KvItem*>(f.ptr<char>(f.o_kvkmv)) + f.kmvsplit[f.chunk[c]];
+        kv.nitems = (int32_t)(f.kmvsplit[f.chunk[c + 1]] - f.kmvsplit[f.chunk[c]]);
+        kv.mode = KV_KMV;
+        prof::timed(prof::OTHER, 0.0, st, [&] { launch_kvec(kv, st); });
+        full_solve(P, I, tJ, tW, c);
+        axpy_chunk(1.0, c);
+        h_chunk(c);
+      }
       // 3. global correction: rho = y_ddot - Sigma_ddot g with exact window solves
       GresArgs gr;
       gr.L = f.ptr<double>(f.o_Lss);
@@ -840,10 +1003,14 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       prof::timed(prof::OTHER, 0.0, st, [&] { launch_gupdate(gr.L, dg, g, tvec, (int)sp, st); });
       // 4. beta -= R_X^-1 K_XS dg  (K_XS dg = V_X^T L_SS^T dg); float32 factors suffice for the correction
       prof::timed(prof::OTHER, 0.0, st, [&] { launch_vdot(f.ptr<double>(f.o_Vt64), tvec, cg, n, (int)sp, st); });
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_gather(f.wt, cg, tJ, tW, (int)M, maxTw, st); });
-      full_solve(P, I, tJ, tW);
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_axpy2(xJ, xW, tJ, tW, -1.0, f.vec_elems, st); });
-      prof::timed(prof::OTHER, 0.0, st, [&] { launch_h(ha, st); });
+      for (int c = 0; c < nch; ++c) {
+        resident(c);
+        const WinTab wc = sub(c);
+        prof::timed(prof::OTHER, 0.0, st, [&] { launch_gather(wc, cg, tJ, tW, nwin(c), maxTw, st); });
+        full_solve(P, I, tJ, tW, c);
+        axpy_chunk(-1.0, c);
+        h_chunk(c);
+      }
       HIPCHK(hipGetLastError());
     }
   }
@@ -918,19 +1085,35 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
 template <typename TW>
 void predict_windows(lma_state& f, Run<TW>& run, int64_t n_u, const std::vector<int64_t>& ubp, const double* Us,
                      const double* VtU, TW* Xbuf, const std::vector<int64_t>& Xoff, TW* winbase, const double* Xs,
-                     const double* Vt, const TW* c) {
-  for (int64_t m = 0; m < f.M; ++m) {
+                     const double* Vt, const TW* c, int64_t m0, int64_t m1, bool refactor) {
+  const int Ts = (int)f.Ts;
+  for (int64_t m = m0; m < m1; ++m) {
     const WinGeom g = win_geom(f.bp, f.M, f.B, m);
     const int64_t qhi = std::min(m + f.B, f.M - 1);
     const int64_t r0 = ubp[m], nr = ubp[qhi + 1] - ubp[m];
     if (nr <= 0) continue;
     const int R = (int)cdiv(nr, TB);
-    run.add_problem(g.T, R, g.tw, true, (int)m);
-    // the stored factor: same descriptors as in the fit
-    add_window_jtiles<TW>(run.rt, g, winbase + f.win_off[m], Xs, Vt, c, f.d, f.sp);
-    // the run's problem-local inverse offset must point at window m's tiles
-    run.pd.back().invdiag_off = 0;
     const int64_t ld = (int64_t)g.T * TB;
+    run.add_problem(g.T, R + (refactor ? Ts + 1 : 0), g.tw, !refactor, (int)m);
+    // the window's rows: the stored factor (solve-only), or generated again with
+    // its support rows and output row so that the factor and the whitened
+    // right-hand sides are rebuilt as in the fit
+    add_window_jtiles<TW>(run.rt, g, winbase + f.win_off[m], Xs, Vt, c, f.d, f.sp);
+    run.pd.back().invdiag_off = win_inv_off(f, m);
+    if (refactor) {
+      TW* rhs = winbase + f.win_off[m] + jpanel_off(g.T);
+      for (int r = 0; r < Ts; ++r) {
+        const int nv = (int)std::min<int64_t>(TB, f.s - (int64_t)r * TB);
+        const bool f64 = std::is_same<TW, double>::value;
+        const double* Ss = f.ptr<double>(f.o_Ss64);
+        RowTile<TW> t = make_tile<TW>(rhs + (int64_t)r * TB * ld, ld, nullptr,
+                                      f64 ? reinterpret_cast<const TW*>(Ss + (int64_t)r * TB * f.d) : nullptr,
+                                      nullptr, nv, TB, SRC_KERNEL, 0);
+        t.xs64 = Ss + (int64_t)r * TB * f.d;
+        run.rt.push_back(t);
+      }
+      run.rt.push_back(make_tile<TW>(rhs + (int64_t)Ts * TB * ld, ld, nullptr, nullptr, nullptr, 1, TB, SRC_CVEC, 0));
+    }
     for (int r = 0; r < R; ++r) {
       const int nv = (int)std::min<int64_t>(TB, nr - (int64_t)r * TB);
       const int64_t pt = r0 + (int64_t)r * TB;
@@ -957,15 +1140,27 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   const int Ts = (int)f.Ts;
   const bool mixed = f.mixed();
   std::vector<int64_t> ubp(u_block_ptr, u_block_ptr + M + 1);
+  // With the window factors held one chunk at a time (memory budget), each
+  // chunk is factored again with the test rows appended, and the test rows'
+  // solutions are kept for one chunk at a time.
+  const bool stream = f.streaming();
+  const int nch = stream ? (int)f.chunk.size() - 1 : 1;
+  std::vector<int64_t> pchunk = stream ? f.chunk : std::vector<int64_t>{0, M};
   // window geometry for test rows
   std::vector<int64_t> Xoff(M, 0);
   int64_t xel = 0;
-  for (int64_t m = 0; m < M; ++m) {
-    const int64_t qhi = std::min(m + f.B, M - 1);
-    const int64_t nr = ubp[qhi + 1] - ubp[m];
-    Xoff[m] = xel;
-    if (var) xel += nr * (int64_t)f.Tm[m] * TB;
+  for (int ci = 0; ci < nch; ++ci) {
+    int64_t acc = 0;
+    for (int64_t m = pchunk[ci]; m < pchunk[ci + 1]; ++m) {
+      const int64_t qhi = std::min(m + f.B, M - 1);
+      const int64_t nr = ubp[qhi + 1] - ubp[m];
+      Xoff[m] = acc;
+      if (var) acc += nr * (int64_t)f.Tm[m] * TB;
+    }
+    xel = std::max(xel, acc);
   }
+  int maxT = 1;
+  for (int64_t m = 0; m < M; ++m) maxT = std::max(maxT, (int)f.Tm[m]);
   const int64_t ldG = sp + TB;
   Arena ar;
   const int64_t o_Us64 = ar.reserve(8 * n_u * d);
@@ -980,20 +1175,21 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   const int64_t o_Tm = ar.reserve(4 * M);
   const int64_t o_twm = ar.reserve(4 * M);
   const int64_t o_stat = ar.reserve(4 * (M + 2));
-  const int64_t o_ld = ar.reserve(8 * 64);
+  const int64_t o_ld = ar.reserve(8 * (M + 2) * (int64_t)maxT);  // log-diagonals of refactored windows
   // runs
   Run<double> runS;
-  Run<TW> runW;
+  std::vector<Run<TW>> runsW(nch);
   Run<double> runD;
   std::vector<GemmTerm<TW>> terms;
   std::vector<GemmOut> outs;
+  std::vector<int> gsplit;  // streaming: G outputs of chunk ci, delta dl: [gsplit[k], gsplit[k+1]), k = ci*(B+1)+dl
   std::vector<KvCol> kvcols;
   std::vector<KvItem> kvitems;
   const int64_t o_hq = ar.reserve(8 * M * sp);
   auto build = [&](char* base) {
     ar.base = base;
     runS = Run<double>();
-    runW = Run<TW>();
+    runsW.assign(nch, Run<TW>());
     runD = Run<double>();
     terms.clear();
     outs.clear();
@@ -1042,47 +1238,53 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     const TW* c = mixed ? (const TW*)f.ptr<float>(f.o_c32) : (const TW*)f.ptr<double>(f.o_c64);
     TW* winbase = reinterpret_cast<TW*>(f.ptr<char>(f.o_win));
     if (!var) return;
-    predict_windows<TW>(f, runW, n_u, ubp, Us, VtU, at<TW>(ar, o_X), Xoff, winbase, Xs, Vt, c);
-    // point each problem at its window's inverted diagonal tiles
-    {
-      int pi = 0;
-      for (int64_t m = 0; m < M; ++m) {
-        const int64_t qhi = std::min(m + f.B, M - 1);
-        if (ubp[qhi + 1] - ubp[m] <= 0) continue;
-        runW.pd[pi++].invdiag_off = win_inv_off(f, m);
-      }
+    for (int ci = 0; ci < nch; ++ci) {
+      predict_windows<TW>(f, runsW[ci], n_u, ubp, Us, VtU, at<TW>(ar, o_X), Xoff, winbase, Xs, Vt, c, f.chunk[ci],
+                          f.chunk[ci + 1], stream);
+      runsW[ci].schedule();
     }
-    runW.schedule();
-    // G accumulation: for delta = 0..B, window m = q - delta contributes to test block q
-    for (int dl = 0; dl <= f.B; ++dl) {
-      for (int64_t q = dl; q < M; ++q) {
-        const int64_t m = q - dl;
-        const int64_t uq = ubp[q + 1] - ubp[q];
-        if (uq <= 0) continue;
-        const WinGeom g = win_geom(f.bp, M, f.B, m);
-        const int64_t ldx = (int64_t)g.T * TB;
-        const TW* Xm = at<TW>(ar, o_X) + Xoff[m] + (ubp[q] - ubp[m]) * ldx;
-        const TW* rhs = winbase + f.win_off[m] + jpanel_off(g.T);
-        for (int64_t t = 0; t < cdiv(uq, TB); ++t) {
-          const int rows = (int)std::min<int64_t>(TB, uq - t * TB);
-          for (int b = 0; b <= Ts; ++b) {
-            GemmOut o = gemm_out(at<double>(ar, o_G) + (ubp[q] + t * TB) * ldG + (int64_t)b * TB, ldG, rows, TB,
-                                 dl > 0 ? 1 : 0, (int)terms.size());
-            GemmTerm<TW> tm;
-            tm.a = Xm + t * TB * ldx;
-            tm.lda = ldx;
-            tm.anr = rows;
-            tm.b = rhs + (int64_t)b * TB * ldx;
-            tm.ldb = ldx;
-            tm.bnr = TB;
-            tm.k0 = dl == 0 ? 0 : g.tw * TB;
-            tm.k1 = g.T * TB;
-            terms.push_back(tm);
-            o.t1 = (int32_t)terms.size();
-            outs.push_back(o);
-          }
+    // G accumulation: window m contributes to test blocks q = m..m+B (delta = q - m)
+    auto g_term = [&](int64_t m, int64_t q, bool accumulate) {
+      const int64_t dl = q - m;
+      const int64_t uq = ubp[q + 1] - ubp[q];
+      if (uq <= 0) return;
+      const WinGeom g = win_geom(f.bp, M, f.B, m);
+      const int64_t ldx = (int64_t)g.T * TB;
+      const TW* Xm = at<TW>(ar, o_X) + Xoff[m] + (ubp[q] - ubp[m]) * ldx;
+      const TW* rhs = winbase + f.win_off[m] + jpanel_off(g.T);
+      for (int64_t t = 0; t < cdiv(uq, TB); ++t) {
+        const int rows = (int)std::min<int64_t>(TB, uq - t * TB);
+        for (int b = 0; b <= Ts; ++b) {
+          GemmOut o = gemm_out(at<double>(ar, o_G) + (ubp[q] + t * TB) * ldG + (int64_t)b * TB, ldG, rows, TB,
+                               accumulate ? 1 : 0, (int)terms.size());
+          GemmTerm<TW> tm;
+          tm.a = Xm + t * TB * ldx;
+          tm.lda = ldx;
+          tm.anr = rows;
+          tm.b = rhs + (int64_t)b * TB * ldx;
+          tm.ldb = ldx;
+          tm.bnr = TB;
+          tm.k0 = dl == 0 ? 0 : g.tw * TB;
+          tm.k1 = g.T * TB;
+          terms.push_back(tm);
+          o.t1 = (int32_t)terms.size();
+          outs.push_back(o);
         }
       }
+    };
+    if (!stream) {
+      // by delta, so that delta = 0 writes each test row's G first
+      for (int dl = 0; dl <= f.B; ++dl)
+        for (int64_t q = dl; q < M; ++q) g_term(q - dl, q, dl > 0);
+    } else {
+      // by chunk of windows, then by delta (G cleared beforehand): within one
+      // launch every window writes different test rows
+      gsplit.assign(1, 0);
+      for (int ci = 0; ci < nch; ++ci)
+        for (int dl = 0; dl <= f.B; ++dl) {
+          for (int64_t m = pchunk[ci]; m < pchunk[ci + 1] && m + dl < M; ++m) g_term(m, m + dl, true);
+          gsplit.push_back((int)outs.size());
+        }
     }
     // Sigma_ddot run in solve-only mode: right-hand sides E_u = k_u - G_u (in place)
     const int Ru = (int)cdiv(n_u, TB);
@@ -1120,7 +1322,9 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     }
     dl_split[f.B + 1] = idx;
   }
-  const int64_t o_meta = ar.reserve(runS.meta_bytes() + runW.meta_bytes() + runD.meta_bytes());
+  int64_t wmeta = 0;
+  for (auto& r : runsW) wmeta += r.meta_bytes();
+  const int64_t o_meta = ar.reserve(runS.meta_bytes() + wmeta + runD.meta_bytes());
   const int64_t o_kvc = ar.reserve(sizeof(KvCol) * std::max<size_t>(kvcols.size(), 1));
   const int64_t o_kvi = ar.reserve(sizeof(KvItem) * std::max<size_t>(kvitems.size(), 1));
   const int64_t o_terms = ar.reserve(sizeof(GemmTerm<TW>) * std::max<size_t>(terms.size(), 1));
@@ -1144,8 +1348,10 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     char* mp = at<char>(ar, o_meta);
     runS.upload(mp, st);
     mp += runS.meta_bytes();
-    runW.upload(mp, st);
-    mp += runW.meta_bytes();
+    for (auto& r : runsW) {
+      r.upload(mp, st);
+      mp += r.meta_bytes();
+    }
     runD.upload(mp, st);
     if (!terms.empty())
       HIPCHK(hipMemcpyAsync(at<char>(ar, o_terms), terms.data(), sizeof(GemmTerm<TW>) * terms.size(),
@@ -1175,7 +1381,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   // scale test inputs
   prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(U, n_u, (int)d, f.ie, at<double>(ar, o_Us64), nullptr, st); });
   HIPCHK(hipGetLastError());
-  auto exec = [&](auto& run, auto* invdiag, int vlen) {
+  auto exec = [&](auto& run, auto* invdiag, int vlen, bool factor = false) {
     using TT = typename std::remove_pointer<decltype(invdiag)>::type;
     StepArgs<TT> a{};
     a.rt = run.d_rt;
@@ -1188,7 +1394,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     a.invdiag = invdiag;
     a.logdiag = ldg;
     a.status = stat;
-    a.maxT = 0;
+    a.maxT = maxT;
     for (int j = 0; j < run.maxT; ++j) {
       a.j = j;
       a.items = run.d_items + run.upd_off[j];
@@ -1197,6 +1403,10 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
       const double fl = prof::on ? run.update_flops(j, vlen > 0 ? f.s : 0, &f64) : 0.0;
       prof::timed(prof::UPDATE, fl, st, [&] { launch_update<TT>(a, std::is_same<TT, float>::value, st); }, f64);
       HIPCHK(hipGetLastError());
+      if (factor) {
+        prof::timed(prof::DIAG, 0.0, st, [&] { launch_diag<TT>(a, run.d_plist + run.pl_off[j], (int)run.pl_n[j], st); });
+        HIPCHK(hipGetLastError());
+      }
       a.items = run.d_items + run.trs_off[j];
       a.nitems = (int32_t)run.trs_n[j];
       prof::timed(prof::TRSM, 0.0, st, [&] { launch_trsm<TT>(a, st); });
@@ -1226,14 +1436,12 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     prof::flush();
     return;
   }
-  exec(runW, reinterpret_cast<TW*>(f.ptr<char>(f.o_win_inv)), (int)sp);
-  for (int dl = 0; dl <= f.B; ++dl) {
-    const int a0 = dl_split[dl], a1 = dl_split[dl + 1];
+  auto g_launch = [&](int a0, int a1) {
     if (a1 > a0)
       prof::timed(prof::GEMM, prof::on ? gemm_flops(terms, outs, a0, a1) : 0.0, st, [&] { launch_tile_gemm<TW>(at<GemmTerm<TW>>(ar, o_terms), at<GemmOut>(ar, o_outs) + a0, a1 - a0, st); });
     HIPCHK(hipGetLastError());
-  }
-  {
+  };
+  auto xi_launch = [&](int64_t m0, int64_t m1, bool accumulate) {
     XiArgs<TW> xa;
     xa.n_u = n_u;
     xa.B = (int)f.B;
@@ -1244,8 +1452,27 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     xa.twm = at<int32_t>(ar, o_twm);
     xa.Xbuf = at<TW>(ar, o_X);
     xa.xi = at<double>(ar, o_xi);
+    xa.m0 = (int32_t)m0;
+    xa.m1 = (int32_t)m1;
+    xa.accumulate = accumulate ? 1 : 0;
     prof::timed(prof::OTHER, 0.0, st, [&] { launch_pred_xi<TW>(xa, st); });
     HIPCHK(hipGetLastError());
+  };
+  TW* invs = reinterpret_cast<TW*>(f.ptr<char>(f.o_win_inv));
+  if (!stream) {
+    exec(runsW[0], invs, (int)sp);
+    for (int dl = 0; dl <= f.B; ++dl) g_launch(dl_split[dl], dl_split[dl + 1]);
+    xi_launch(0, M, false);
+  } else {
+    HIPCHK(hipMemsetAsync(at<double>(ar, o_G), 0, 8 * n_u * ldG, st));
+    for (int ci = 0; ci < nch; ++ci) {
+      exec(runsW[ci], invs, (int)sp, true);
+      for (int dl = 0; dl <= f.B; ++dl) {
+        const int k = ci * ((int)f.B + 1) + dl;
+        g_launch(gsplit[k], gsplit[k + 1]);
+      }
+      xi_launch(pchunk[ci], pchunk[ci + 1], ci > 0);
+    }
   }
   PredArgs pa;
   pa.n_u = n_u;
@@ -1362,6 +1589,10 @@ lma_status lma_state_lml(const lma_state* f, double* lml) {
 }
 
 void lma_free(lma_state* f) { delete f; }
+
+int64_t lma_state_bytes(const lma_state* f) { return f ? f->ar.cap : -1; }
+
+int64_t lma_state_chunks(const lma_state* f) { return f ? (int64_t)f->chunk.size() - 1 : -1; }
 
 const char* lma_last_error(void) { return g_err.c_str(); }
 

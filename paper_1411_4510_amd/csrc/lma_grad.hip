@@ -74,13 +74,16 @@ void add_ex(DcItem& it, const double* e, int64_t ld, double s) {
   ++it.nex;
 }
 
-// solve-only steps of an engine run (right-hand sides only)
+// Steps of an engine run: solve-only (right-hand sides against stored factors),
+// or (factor) factorisation and solves, with the window run's arithmetic; the
+// log-diagonals go to ldg[problem * maxT + column].
 template <typename TT>
-void solve_steps(Run<TT>& run, TT* invdiag, const lma_state& f, double* ldg, int32_t* stat, hipStream_t st) {
+void solve_steps(Run<TT>& run, TT* invdiag, const lma_state& f, double* ldg, int32_t* stat, hipStream_t st,
+                 bool factor = false, int maxT = 0) {
   StepArgs<TT> a{};
   a.rt = run.d_rt;
   a.pd = run.d_pd;
-  a.vlen = 0;
+  a.vlen = factor ? (int)f.sp : 0;
   a.vld = f.sp;
   a.d = (int)f.d;
   a.sf2 = f.sf2;
@@ -88,15 +91,19 @@ void solve_steps(Run<TT>& run, TT* invdiag, const lma_state& f, double* ldg, int
   a.invdiag = invdiag;
   a.logdiag = ldg;
   a.status = stat;
-  a.maxT = 0;
+  a.maxT = maxT;
   for (int j = 0; j < run.maxT; ++j) {
     a.j = j;
     a.items = run.d_items + run.upd_off[j];
     a.nitems = (int32_t)run.upd_n[j];
     double f64 = 0.0;
-    const double fl = prof::on ? run.update_flops(j, 0, &f64) : 0.0;
-    prof::timed(prof::UPDATE, fl, st, [&] { launch_update<TT>(a, false, st); }, f64);
+    const double fl = prof::on ? run.update_flops(j, factor ? f.s : 0, &f64) : 0.0;
+    prof::timed(prof::UPDATE, fl, st, [&] { launch_update<TT>(a, factor && std::is_same<TT, float>::value, st); }, f64);
     HIPCHK(hipGetLastError());
+    if (factor) {
+      prof::timed(prof::DIAG, 0.0, st, [&] { launch_diag<TT>(a, run.d_plist + run.pl_off[j], (int)run.pl_n[j], st); });
+      HIPCHK(hipGetLastError());
+    }
     a.items = run.d_items + run.trs_off[j];
     a.nitems = (int32_t)run.trs_n[j];
     prof::timed(prof::TRSM, 0.0, st, [&] { launch_trsm<TT>(a, st); });
@@ -180,9 +187,12 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, T
   {
     int64_t acc = 0;
     cbeg.push_back(0);
+    size_t fc = 1;  // next boundary of the fit's window chunks
     for (int64_t m = 0; m < M; ++m) {
       const int64_t b = win_bytes(m);
-      if (acc > 0 && acc + b > budget) {
+      const bool fit_cut = f.streaming() && fc + 1 < f.chunk.size() && m == f.chunk[fc];
+      if (fit_cut) ++fc;
+      if (acc > 0 && (fit_cut || acc + b > budget)) {
         cbeg.push_back(m);
         acc = 0;
       }
@@ -240,7 +250,10 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, T
   const int64_t o_uW = ar.reserve(8 * M * sp);
   const int64_t o_Omp = ar.reserve(8 * (int64_t)Go * sp2);
   const int64_t o_gdev = ar.reserve(8 * ncomp);
-  const int64_t o_stat = ar.reserve(8 * 64);
+  int maxTw = 1;
+  for (int64_t m = 0; m < M; ++m) maxTw = std::max(maxTw, (int)f.Tm[m]);
+  const int64_t o_stat = ar.reserve(4 * (M + 2));
+  const int64_t o_ldg = ar.reserve(8 * (M + 2) * (int64_t)std::max(maxTw, Ts));
   const int64_t o_X = ar.reserve(xcap);
   const int64_t o_D = ar.reserve(8 * dcap);
 
@@ -340,9 +353,26 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, T
       Run<TW>& run = runX[c];
       for (int64_t m = cbeg[c]; m < cbeg[c + 1]; ++m) {
         const WinGeom& g = geo[m];
-        run.add_problem(g.T, g.T, 0, true, (int)m);
+        // factors held one chunk at a time: factor the window again, with its
+        // support rows and output row, before the identity rows
+        const bool refactor = f.streaming();
+        run.add_problem(g.T, g.T + (refactor ? Ts + 1 : 0), g.tw, !refactor, (int)m);
         add_window_jtiles<TW>(run.rt, g, winbase + f.win_off[m], Xs, Vt, cvec, d, sp);
         run.pd.back().invdiag_off = win_inv_off(f, m);
+        if (refactor) {
+          TW* rhs = winbase + f.win_off[m] + jpanel_off(g.T);
+          const int64_t ldr = (int64_t)g.T * TB;
+          for (int r = 0; r < Ts; ++r) {
+            const int nv = (int)std::min<int64_t>(TB, s - (int64_t)r * TB);
+            const bool f64 = std::is_same<TW, double>::value;
+            RowTile<TW> t = make_tile<TW>(rhs + (int64_t)r * TB * ldr, ldr, nullptr,
+                                          f64 ? reinterpret_cast<const TW*>(Ss + (int64_t)r * TB * d) : nullptr,
+                                          nullptr, nv, TB, SRC_KERNEL, 0);
+            t.xs64 = Ss + (int64_t)r * TB * d;
+            run.rt.push_back(t);
+          }
+          run.rt.push_back(make_tile<TW>(rhs + (int64_t)Ts * TB * ldr, ldr, nullptr, nullptr, nullptr, 1, TB, SRC_CVEC, 0));
+        }
         TW* Xm = reinterpret_cast<TW*>(reinterpret_cast<char*>(Xb) + xoff[m]);
         for (int r = 0; r < g.T; ++r) {
           RowTile<TW> t = make_tile<TW>(Xm + tri_off(g.T, r), (int64_t)(g.T - r) * TB, nullptr, nullptr, nullptr, TB,
@@ -695,7 +725,7 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, T
 
   double* part = at<double>(ar, o_part);
   int32_t* stat = at<int32_t>(ar, o_stat);
-  double* ldg = at<double>(ar, o_stat) + 8;
+  double* ldg = at<double>(ar, o_ldg);
   auto gemm_d = [&](const GemmBatch& b) {
     if (b.o1 > b.o0)
       prof::timed(prof::GEMM, prof::on ? gemm_flops(d_terms, outs_d, b.o0, b.o1) : 0.0, st,
@@ -749,7 +779,7 @@ void grad_run(lma_state& f, double* grad_host, int64_t budget, hipStream_t st, T
   HIPCHK(hipGetLastError());
   // ---- window chunks
   for (int c = 0; c < nchunk; ++c) {
-    solve_steps<TW>(runX[c], wininv, f, ldg, stat, st);
+    solve_steps<TW>(runX[c], wininv, f, ldg, stat, st, f.streaming(), maxTw);
     for (const GemmBatch& b : {c2[c], c2b[c]})
       if (b.o1 > b.o0)
         prof::timed(prof::GEMM, prof::on ? gemm_flops(tw_terms, outs_tw, b.o0, b.o1) : 0.0, st, [&] {

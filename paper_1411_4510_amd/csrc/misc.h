@@ -60,6 +60,8 @@ struct XiArgs {
   const int32_t* twm;    // column tiles of W_m
   const T* Xbuf;
   double* xi;
+  int32_t m0, m1;        // only windows m0 <= m < m1 contribute
+  int32_t accumulate;    // 1: add to xi, 0: overwrite
 };
 
 void launch_scale(const double* X, int64_t n, int d, const InvEll& ie, double* o64, float* o32, hipStream_t st);

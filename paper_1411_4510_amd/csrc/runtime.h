@@ -260,11 +260,22 @@ struct lma_state {
   std::vector<int32_t> Tm, twm;
   std::vector<int64_t> win_off;     // element offset of window m's panels
   std::vector<int64_t> rhs_off;     // element offset of window m's RHS panel (support rows then c row)
+  std::vector<int64_t> inv_off;     // element offset of window m's inverted diagonal tiles
+  // Window chunks [chunk[c], chunk[c+1]): the windows whose factors are resident
+  // together.  One chunk holds all windows unless mem_budget_bytes is too small
+  // for that; then win_off / inv_off are relative to the chunk's first window,
+  // the window area holds one chunk at a time, and every pass that needs the
+  // factors refactors chunk by chunk.
+  std::vector<int64_t> chunk;
+  int64_t win_area = 0, inv_area = 0;  // elements of the window areas
+  std::vector<int64_t> sumsplit;    // summary outputs of chunk c: [sumsplit[c], sumsplit[c+1])
+  std::vector<int64_t> kmvsplit;    // KV_KMV items of window m start at kmvsplit[m] ([M+1])
+  bool streaming() const { return chunk.size() > 2; }
   int groups = 1, ntile = 1;
   // runs
   lmart::Run<double> runS;
-  lmart::Run<float> runW32;
-  lmart::Run<double> runW64;
+  std::vector<lmart::Run<float>> runsW32;   // window runs, one per chunk
+  std::vector<lmart::Run<double>> runsW64;
   lmart::Run<double> runD;
   std::vector<lma::GemmTerm<double>> sum64;
   std::vector<lma::GemmTerm<float>> sum32;
@@ -426,12 +437,8 @@ void add_s_jtiles(std::vector<RowTile<T>>& rt, T* base, const T* Ss, int64_t s, 
   }
 }
 
-// Inverted diagonal tiles of window m start at the sum of T_k*TB*TB over k < m.
-inline int64_t win_inv_off(const lma_state& f, int64_t m) {
-  int64_t o = 0;
-  for (int64_t k = 0; k < m; ++k) o += (int64_t)f.Tm[k] * TB * TB;
-  return o;
-}
+// Inverted diagonal tiles of window m (element offset in the inverse area).
+inline int64_t win_inv_off(const lma_state& f, int64_t m) { return f.inv_off[m]; }
 
 // Likelihood gradient of a fitted state (lma_grad.hip): grad[d+2] (host) receives
 // d LML / d (log l_1..log l_d, log sigma_s^2, log sigma_n^2).  Windows are

@@ -344,6 +344,7 @@ void launch_gather(const WinTab& w, const double* pt, double* vJ, double* vW, in
 }
 void launch_axpy2(double* vJ, double* vW, const double* xJ, const double* xW, double alpha, int64_t nvec,
                   hipStream_t st) {
+  if (nvec <= 0) return;
   const int nb = (int)std::min<int64_t>((nvec + 255) / 256, 65536);
   hipLaunchKernelGGL(k_axpy2, dim3(nb), dim3(256), 0, st, vJ, vW, xJ, xW, alpha, nvec);
 }

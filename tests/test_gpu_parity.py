@@ -88,6 +88,46 @@ def test_band_and_on_the_fly_entries_agree(lib, monkeypatch, precision):
     assert abs(a[2] - b[2]) <= agree * abs(b[2])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_memory_budget_streams_window_factors(lib, precision):
+    """A memory budget below the resident state's size: the fit keeps one chunk
+    of window factors at a time, and prediction and the gradient factor the
+    windows again chunk by chunk.  Results match the oracle, and the resident
+    path within rounding; a budget that cannot hold one window is an error."""
+    p = synth.make_random(seed=23, n=2600, d=3, M=7, s=150, n_u=300, B=2, uneven=(150, 650), name="budget")
+    ref = olma.fit_predict(p)
+    st = lib.fit_problem(p, precision=precision)
+    full, nch = st.nbytes(), st.chunks()
+    m0, v0 = (t.cpu().numpy() for t in st.predict(p.U, p.u_block_ptr))
+    l0 = st.lml()
+    st.free()
+    assert nch == 1
+    budget = int(0.6 * full)
+    st = lib.fit_problem(p, precision=precision, mem_budget=budget)
+    nbytes, nch = st.nbytes(), st.chunks()
+    m1, v1 = (t.cpu().numpy() for t in st.predict(p.U, p.u_block_ptr))
+    l1 = st.lml()
+    st.free()
+    print(f"  resident {full} bytes; budget {budget}: {nbytes} bytes in {nch} chunks", flush=True)
+    assert nch >= 2 and nbytes <= budget
+    tol = TOL[precision]
+    assert rel(m1, ref["mean"]) <= tol and rel(v1, ref["var"]) <= tol
+    assert abs(l1 - ref["lml"]) <= tol * abs(ref["lml"])
+    agree = {"fp64": 1e-11, "mixed": 1e-6}[precision]
+    print(f"  streamed vs resident: mean {rel(m1, m0):.2e} var {rel(v1, v0):.2e} "
+          f"lml {abs(l1 - l0) / abs(l0):.2e}", flush=True)
+    assert rel(m1, m0) <= agree and rel(v1, v0) <= agree and abs(l1 - l0) <= agree * abs(l0)
+    la, ga = lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, precision=precision, grad=True)
+    lb, gb = lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, precision=precision, grad=True,
+                     mem_budget=budget)
+    lo, go = olma.lml_grad(p)
+    print(f"  gradient streamed vs resident {rel(gb, ga):.2e}, vs oracle {rel(gb, go):.2e}", flush=True)
+    assert abs(lb - la) <= agree * abs(la) and rel(gb, ga) <= 1e3 * agree
+    assert abs(lb - lo) <= tol * abs(lo) and rel(gb, go) <= tol
+    with pytest.raises(lib.LmaError):
+        lib.fit_problem(p, precision=precision, mem_budget=1 << 20)
+
+
 def test_fp64_is_deterministic(lib):
     p = synth.make_random(seed=5, n=900, d=3, M=5, s=70, n_u=100, B=2, uneven=(100, 250))
     a = gpu_fit_predict(lib, p, "fp64")
