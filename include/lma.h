@@ -120,7 +120,7 @@ lma_status lma_predict(lma_state *f, int64_t n_u, const double *U, const int64_t
 lma_status lma_lml(const lma_problem *p, double *lml, double *grad, hipStream_t stream);
 
 /* Release a state (NULL is ignored).  Its device memory is kept for reuse by
- * the next lma_fit / lma_predict of a similar size (at most two blocks are
+ * the next lma_fit / lma_predict of a similar size (at most four blocks are
  * kept per process); lma_release_cache() hands them back to the runtime. */
 void lma_free(lma_state *f);
 

@@ -51,8 +51,8 @@ T* at(const Arena& ar, int64_t off) {
   return reinterpret_cast<T*>(ar.base + off);
 }
 
-// Device blocks released by lma_free / lma_predict are kept (at most two) and
-// reused by the next call that fits in them (see lma.hip).
+// Device blocks released by lma_free / lma_predict / the end of a fit are kept
+// (at most four) and reused by the next call that fits in them (see lma.hip).
 namespace devcache {
 void* get(size_t bytes);
 void put(void* p, size_t bytes);
