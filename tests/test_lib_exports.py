@@ -49,6 +49,52 @@ def test_version_and_error_without_gpu(so):
     assert "NULL" in so.lma_last_error().decode()
 
 
+BAD_PROBLEMS = [
+    ("d = 0", dict(d=0)),
+    ("d = 65", dict(d=65)),
+    ("n = 0", dict(n=0)),
+    ("s = 0", dict(s=0)),
+    ("B < 0", dict(B=-1)),
+    ("more blocks than points", dict(M=20)),
+    ("block_ptr not ending at n", dict(bp=[0, 3, 6, 9])),
+    ("empty block", dict(bp=[0, 3, 3, 10])),
+    ("unknown precision", dict(precision=7)),
+    ("reserved field set", dict(reserved=1)),
+    ("non-finite hyperparameter", dict(log_hyp=[0.0, float("nan"), 0.0, 0.0])),
+    ("non-finite prior mean", dict(prior_mean=float("inf"))),
+    ("support set beyond 8192", dict(s=8193)),
+    ("NULL X", dict(X=None)),
+]
+
+
+@pytest.mark.parametrize("what,kw", BAD_PROBLEMS, ids=[b[0] for b in BAD_PROBLEMS])
+def test_bad_problems_rejected_on_the_host(so, what, kw):
+    """Argument errors come back as LMA_E_ARG with a message before any device
+    call (the arrays are host dummies: only their presence is checked)."""
+    so.lma_fit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    so.lma_fit.restype = ctypes.c_int
+    so.lma_last_error.restype = ctypes.c_char_p
+    dummy = (ctypes.c_double * 64)()
+    bp = (ctypes.c_int64 * 4)(*kw.get("bp", [0, 3, 6, 10]))
+    lh = (ctypes.c_double * 4)(*kw.get("log_hyp", [0.0, 0.0, 0.0, -2.0]))
+    pr = lma._Problem()
+    pr.n, pr.d, pr.s = kw.get("n", 10), kw.get("d", 2), kw.get("s", 4)
+    pr.M, pr.B = kw.get("M", 3), kw.get("B", 1)
+    addr = ctypes.cast(dummy, ctypes.c_void_p).value
+    pr.X = kw.get("X", addr)
+    pr.y = addr
+    pr.S = addr
+    pr.block_ptr = ctypes.cast(bp, ctypes.POINTER(ctypes.c_int64))
+    pr.log_hyp = ctypes.cast(lh, ctypes.POINTER(ctypes.c_double))
+    pr.prior_mean = kw.get("prior_mean", 0.0)
+    pr.precision = kw.get("precision", 0)
+    pr.reserved = kw.get("reserved", 0)
+    h = ctypes.c_void_p()
+    assert so.lma_fit(ctypes.byref(pr), None, ctypes.byref(h)) == lma.LMA_E_ARG, what
+    assert not h.value
+    assert so.lma_last_error().decode()
+
+
 def test_binding_struct_matches_header_layout():
     # lma_problem: 5 int64, 6 pointers/doubles in order, then int32 x2 and int64
     assert ctypes.sizeof(lma._Problem) == 5 * 8 + 5 * 8 + 8 + 4 + 4 + 8
