@@ -304,6 +304,31 @@ __global__ __launch_bounds__(NT) void k_band(BandArgs<T> a) {
   wave_gemm<double, double>(acc, a.Vt + it.p0 * a.vld, a.vld, it.nr, a.Vt + it.q0 * a.vld, a.vld, it.nc, 0, a.vlen,
                             wr * 64, wc * 64, lane);
   __syncthreads();
+  // squared distances of the lane's 64 entries, one coordinate at a time (its 16
+  // row and 4 column values of a coordinate are read from LDS once)
+  double sq[4][4][4];
+#pragma unroll
+  for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sq[rs][cs][v] = 0.0;
+  for (int t = 0; t < d; ++t) {
+    double cv[4];
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs) cv[cs] = xc[t * TB + wc * 64 + cs * 16 + (lane & 15)];
+#pragma unroll
+    for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double rv = xr[t * TB + wr * 64 + rs * 16 + Mfma<double>::row(lane, v)];
+#pragma unroll
+        for (int cs = 0; cs < 4; ++cs) {
+          const double df = rv - cv[cs];
+          sq[rs][cs][v] += df * df;
+        }
+      }
+  }
 #pragma unroll
   for (int rs = 0; rs < 4; ++rs)
 #pragma unroll
@@ -313,12 +338,7 @@ __global__ __launch_bounds__(NT) void k_band(BandArgs<T> a) {
         const int row = wr * 64 + rs * 16 + Mfma<double>::row(lane, v);
         const int col = wc * 64 + cs * 16 + (lane & 15);
         if (row < it.nr && col < it.nc) {
-          double sq = 0.0;
-          for (int t = 0; t < d; ++t) {
-            const double df = xr[t * TB + row] - xc[t * TB + col];
-            sq += df * df;
-          }
-          double kv = a.sf2 * k_exp(-0.5 * sq);
+          double kv = a.sf2 * k_exp(-0.5 * sq[rs][cs][v]);
           if (it.p0 + row == it.q0 + col) kv += a.sn2;
           a.band[it.off + (int64_t)row * it.ld + col] = (T)(kv - acc[rs][cs][v]);
         }

@@ -52,6 +52,30 @@ __global__ __launch_bounds__(NT) void k_dcontract(DcArgs<TX> a) {
   }
   __syncthreads();
 
+  // squared distances of the lane's 64 entries, one length-scale at a time
+  double dist[4][4][4];
+#pragma unroll
+  for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) dist[rs][cs][v] = 0.0;
+  for (int q = 0; q < d; ++q) {
+    double cv[4];
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs) cv[cs] = xc[q * TB + wc * 64 + cs * 16 + (lane & 15)];
+#pragma unroll
+    for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double rv = xr[q * TB + wr * 64 + rs * 16 + Mfma<double>::row(lane, v)];
+#pragma unroll
+        for (int cs = 0; cs < 4; ++cs) {
+          const double df = rv - cv[cs];
+          dist[rs][cs][v] += df * df;
+        }
+      }
+  }
   // pass 1: e_ij = wt * A_ij * k_ij (kept in acc), signal and noise sums
   const bool same_diag = it.kind == DC_SAME && it.diag;
   const double sf2 = a.sf2, sn2 = a.sn2;
@@ -73,12 +97,7 @@ __global__ __launch_bounds__(NT) void k_dcontract(DcArgs<TX> a) {
 #pragma unroll
           for (int x = 0; x < 2; ++x)
             if (x < it.nex) val += it.exs[x] * it.ex[x][(int64_t)row * it.exld[x] + col];
-          double dist = 0.0;
-          for (int q = 0; q < d; ++q) {
-            const double df = xr[q * TB + row] - xc[q * TB + col];
-            dist += df * df;
-          }
-          e = it.wt * val * (sf2 * exp(-0.5 * dist));
+          e = it.wt * val * (sf2 * exp(-0.5 * dist[rs][cs][v]));
           gs += e;
           if (same_diag && row == col) gn += it.wt * val * sn2;
         }
