@@ -63,6 +63,32 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
   T* out = ri.panel + (int64_t)(a.j - ri.kbeg) * TB;
   const bool ident = ri.src == SRC_IDENT;
   const bool ident_here = ident && ri.kbeg == a.j;
+  // squared distances of the lane's 64 entries, one coordinate at a time
+  TK sq[4][4][4];
+#pragma unroll
+  for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sq[rs][cs][v] = TK(0);
+  if (kern) {
+    for (int t = 0; t < d; ++t) {
+      TK cv[4];
+#pragma unroll
+      for (int cs = 0; cs < 4; ++cs) cv[cs] = xc[t * TB + wc * 64 + cs * 16 + (lane & 15)];
+#pragma unroll
+      for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const TK rv = xr[t * TB + wr * 64 + rs * 16 + Mfma<TK>::row(lane, v)];
+#pragma unroll
+          for (int cs = 0; cs < 4; ++cs) {
+            const TK df = rv - cv[cs];
+            sq[rs][cs][v] += df * df;
+          }
+        }
+    }
+  }
 #pragma unroll
   for (int rs = 0; rs < 4; ++rs) {
 #pragma unroll
@@ -76,12 +102,7 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
           kv = (ident_here && row == col) ? TK(1) : TK(0);  // exact at padding too
         } else if (row < ri.nvalid && col < rj.nvalid) {
           if (kern) {
-            TK s = TK(0);
-            for (int t = 0; t < d; ++t) {
-              const TK df = xr[t * TB + row] - xc[t * TB + col];
-              s += df * df;
-            }
-            kv = sf2 * k_exp(TK(-0.5) * s);
+            kv = sf2 * k_exp(TK(-0.5) * sq[rs][cs][v]);
             if (diag && row == col) kv += sn2;
           } else if (band) {
             const int64_t p = ri.pt0 + row, q = rj.pt0 + col;
@@ -290,7 +311,7 @@ __global__ __launch_bounds__(NT) void k_band(BandArgs<T> a) {
   if (logical >= a.nitems) return;
   const BandItem it = a.items[logical];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, wr = w >> 1, wc = w & 1;
-  // coordinates first: their loads complete while the V products run
+  // coordinates of the tile's row and column points
   const int d = a.d;
   double* xr = reinterpret_cast<double*>(smem_raw);  // [d][TB]
   double* xc = xr + d * TB;
