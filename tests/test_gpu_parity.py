@@ -88,13 +88,13 @@ def test_band_and_on_the_fly_entries_agree(lib, monkeypatch, precision):
     assert abs(a[2] - b[2]) <= agree * abs(b[2])
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_memory_budget_streams_window_factors(lib, precision):
+@pytest.mark.parametrize("precision,B", [("fp64", 2), ("mixed", 2), ("fp64", 0), ("mixed", 6)])
+def test_memory_budget_streams_window_factors(lib, precision, B):
     """A memory budget below the resident state's size: the fit keeps one chunk
     of window factors at a time, and prediction and the gradient factor the
     windows again chunk by chunk.  Results match the oracle, and the resident
     path within rounding; a budget that cannot hold one window is an error."""
-    p = synth.make_random(seed=23, n=2600, d=3, M=7, s=150, n_u=300, B=2, uneven=(150, 650), name="budget")
+    p = synth.make_random(seed=23, n=2600, d=3, M=7, s=150, n_u=300, B=B, uneven=(150, 650), name="budget")
     ref = olma.fit_predict(p)
     st = lib.fit_problem(p, precision=precision)
     full, nch = st.nbytes(), st.chunks()
