@@ -141,7 +141,7 @@ def main():
                     help="only run a plain device copy of MIB mebibytes (to scale HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(see the sharding design); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
