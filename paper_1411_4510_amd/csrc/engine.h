@@ -38,7 +38,11 @@ constexpr int DIAG_LD = TB + 1;
 // overlap, so each point pair of the band is formed once instead of once per
 // window that holds it.  Row and column tiles are runs of consecutive
 // training points starting at pt0.
-enum Src : int32_t { SRC_KERNEL = 0, SRC_EXPLICIT = 1, SRC_CVEC = 2, SRC_IDENT = 3, SRC_BAND = 4 };
+// SRC_TBAND: right-hand-side rows of test points whose residual cross
+// covariances R_ux = K_ux - V_u.V_x with the window's training points are read
+// from a precomputed test band (entry (u, x) at band[brow[u] + x]); a test point
+// sits in B+1 windows, each of which would otherwise form them again.
+enum Src : int32_t { SRC_KERNEL = 0, SRC_EXPLICIT = 1, SRC_CVEC = 2, SRC_IDENT = 3, SRC_BAND = 4, SRC_TBAND = 5 };
 
 template <typename T>
 struct RowTile {
@@ -57,7 +61,7 @@ struct RowTile {
   int32_t is_j;      // 1 for rows of the matrix being factored
   int32_t kbeg;      // first column tile stored (the row is zero to its left); 0 except SRC_IDENT
   int32_t pad_;
-  int64_t pt0;       // SRC_BAND: training index of the tile's first row
+  int64_t pt0;       // SRC_BAND / SRC_TBAND: index of the tile's first row point (its own point set)
 };
 
 struct ProbDesc {
@@ -89,7 +93,8 @@ struct StepArgs {
   int32_t* status;    // [problem], set to 1 when a pivot is not positive
   int32_t maxT;
   // residual band of the SRC_BAND rows: entry (p, q) with q <= p at band[brow[p] + q]
-  // (the other triangle by symmetry); null when no row of the run uses it
+  // (the other triangle by symmetry); for SRC_TBAND rows the test band, entry
+  // (u, x) at band[brow[u] + x]; null when no row of the run uses one
   const T* band;
   const int64_t* brow;
 };
@@ -113,10 +118,12 @@ struct BandArgs {
   int32_t nitems;
   int32_t d;
   int32_t vlen;       // length of the whitened support rows (multiple of 16)
-  int32_t pad_;
+  int32_t noise;      // 1: add sn2 where the row and column index agree (rows and columns are one point set)
   int64_t vld;
-  const double* Vt;   // whitened support rows [n][vld]
-  const double* Xs;   // length-scaled coordinates [n][d]
+  const double* Vt;   // whitened support rows of the column points [.][vld]
+  const double* Xs;   // length-scaled coordinates of the column points [.][d]
+  const double* Vr;   // the same for the row points (a test band: the test points)
+  const double* Xr;
   double sf2, sn2;
   T* band;
 };

@@ -29,8 +29,9 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
   if constexpr (MIXED) zero_acc<T>(accl);
   const TK* vi = MIXED ? (const TK*)ri.vt64 : (const TK*)ri.vt;
   const TK* vj = MIXED ? (const TK*)rj.vt64 : (const TK*)rj.vt;
-  const bool band = ri.src == SRC_BAND;  // V part already inside the band entries
-  if (!band && vi != nullptr && vj != nullptr && a.vlen > 0)
+  const bool band = ri.src == SRC_BAND;    // V part already inside the band entries
+  const bool tband = ri.src == SRC_TBAND;  // likewise for test rows
+  if (!band && !tband && vi != nullptr && vj != nullptr && a.vlen > 0)
     wave_gemm<TK, TK>(accv, vi, a.vld, ri.nvalid, vj, a.vld, rj.nvalid, 0, a.vlen, wr * 64, wc * 64, lane);
   // factor columns kb .. j-1 (a row is zero left of its kbeg)
   const int kb = ri.kbeg > rj.kbeg ? ri.kbeg : rj.kbeg;
@@ -107,6 +108,8 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
           } else if (band) {
             const int64_t p = ri.pt0 + row, q = rj.pt0 + col;
             kv = (TK)(q <= p ? a.band[a.brow[p] + q] : a.band[a.brow[q] + p]);
+          } else if (tband) {
+            kv = (TK)a.band[a.brow[ri.pt0 + row] + rj.pt0 + col];
           } else if (ri.src == SRC_EXPLICIT) {
             kv = (TK)ri.expl[(int64_t)row * ri.eld + (int64_t)a.j * TB + col];
           } else {
@@ -317,12 +320,12 @@ __global__ __launch_bounds__(NT) void k_band(BandArgs<T> a) {
   double* xc = xr + d * TB;
   for (int idx = tid; idx < TB * d; idx += NT) {
     const int r = idx / d, t = idx - r * d;
-    xr[t * TB + r] = r < it.nr ? a.Xs[(it.p0 + r) * d + t] : 0.0;
+    xr[t * TB + r] = r < it.nr ? a.Xr[(it.p0 + r) * d + t] : 0.0;
     xc[t * TB + r] = r < it.nc ? a.Xs[(it.q0 + r) * d + t] : 0.0;
   }
   typename Mfma<double>::acc acc[4][4];
   zero_acc<double>(acc);
-  wave_gemm<double, double>(acc, a.Vt + it.p0 * a.vld, a.vld, it.nr, a.Vt + it.q0 * a.vld, a.vld, it.nc, 0, a.vlen,
+  wave_gemm<double, double>(acc, a.Vr + it.p0 * a.vld, a.vld, it.nr, a.Vt + it.q0 * a.vld, a.vld, it.nc, 0, a.vlen,
                             wr * 64, wc * 64, lane);
   __syncthreads();
   // squared distances of the lane's 64 entries, one coordinate at a time (its 16
@@ -360,7 +363,7 @@ __global__ __launch_bounds__(NT) void k_band(BandArgs<T> a) {
         const int col = wc * 64 + cs * 16 + (lane & 15);
         if (row < it.nr && col < it.nc) {
           double kv = a.sf2 * k_exp(-0.5 * sq[rs][cs][v]);
-          if (it.p0 + row == it.q0 + col) kv += a.sn2;
+          if (a.noise && it.p0 + row == it.q0 + col) kv += a.sn2;
           a.band[it.off + (int64_t)row * it.ld + col] = (T)(kv - acc[rs][cs][v]);
         }
       }

@@ -753,6 +753,9 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
       ba.vld = sp;
       ba.Vt = f.ptr<double>(f.o_Vt64);
       ba.Xs = f.ptr<double>(f.o_Xs64);
+      ba.Vr = ba.Vt;
+      ba.Xr = ba.Xs;
+      ba.noise = 1;
       ba.sf2 = f.sf2;
       ba.sn2 = f.sn2;
       ba.band = band;
@@ -1085,7 +1088,7 @@ lma_status do_fit(const lma_problem* p, hipStream_t st, lma_state** out, bool ke
 template <typename TW>
 void predict_windows(lma_state& f, Run<TW>& run, int64_t n_u, const std::vector<int64_t>& ubp, const double* Us,
                      const double* VtU, TW* Xbuf, const std::vector<int64_t>& Xoff, TW* winbase, const double* Xs,
-                     const double* Vt, const TW* c, int64_t m0, int64_t m1, bool refactor) {
+                     const double* Vt, const TW* c, int64_t m0, int64_t m1, bool refactor, bool tband) {
   const int Ts = (int)f.Ts;
   for (int64_t m = m0; m < m1; ++m) {
     const WinGeom g = win_geom(f.bp, f.M, f.B, m);
@@ -1124,6 +1127,8 @@ void predict_windows(lma_state& f, Run<TW>& run, int64_t n_u, const std::vector<
                                     SRC_KERNEL, 0);
       t.vt64 = VtU + pt * f.sp;
       t.xs64 = Us + pt * f.d;
+      t.pt0 = pt;
+      if (tband) t.src = SRC_TBAND;
       run.rt.push_back(t);
     }
   }
@@ -1145,6 +1150,39 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   // solutions are kept for one chunk at a time.
   const bool stream = f.streaming();
   const int nch = stream ? (int)f.chunk.size() - 1 : 1;
+  // Test band: R_ux for every test point u of block q and every training point x
+  // of blocks q-B .. q+B (all windows that hold u lie there), formed once and
+  // read by the B+1 window solves of u (not in the memory-budget mode).
+  const int64_t wsz = (int64_t)sizeof(TW);
+  const bool use_tband = var != nullptr && n_u > 0 && !stream && std::getenv("LMA_NO_BAND") == nullptr;
+  std::vector<BandItem> tb_items;
+  std::vector<int64_t> tb_row;
+  int64_t tb_elems = 0;
+  if (use_tband) {
+    tb_row.resize(n_u);
+    for (int64_t q = 0; q < M; ++q) {
+      const int64_t r0 = ubp[q], r1 = ubp[q + 1];
+      if (r1 <= r0) continue;
+      const int64_t c0 = f.bp[std::max<int64_t>(0, q - f.B)], c1 = f.bp[std::min<int64_t>(M - 1, q + f.B) + 1];
+      const int64_t w = c1 - c0;
+      for (int64_t u = r0; u < r1; ++u) tb_row[u] = tb_elems + (u - r0) * w - c0;
+      for (int64_t g0 = r0; g0 < r1; g0 += 4 * TB) {
+        const int64_t g1 = std::min<int64_t>(r1, g0 + 4 * TB);
+        for (int64_t x0 = c0; x0 < c1; x0 += TB)
+          for (int64_t u0 = g0; u0 < g1; u0 += TB) {
+            BandItem it;
+            it.p0 = u0;
+            it.q0 = x0;
+            it.off = tb_elems + (u0 - r0) * w + (x0 - c0);
+            it.ld = w;
+            it.nr = (int)std::min<int64_t>(TB, r1 - u0);
+            it.nc = (int)std::min<int64_t>(TB, c1 - x0);
+            tb_items.push_back(it);
+          }
+      }
+      tb_elems += (r1 - r0) * w;
+    }
+  }
   std::vector<int64_t> pchunk = stream ? f.chunk : std::vector<int64_t>{0, M};
   // window geometry for test rows
   std::vector<int64_t> Xoff(M, 0);
@@ -1186,6 +1224,9 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   std::vector<KvCol> kvcols;
   std::vector<KvItem> kvitems;
   const int64_t o_hq = ar.reserve(8 * M * sp);
+  const int64_t o_tb = ar.reserve(wsz * std::max<int64_t>(tb_elems, 1));
+  const int64_t o_tbi = ar.reserve((int64_t)sizeof(BandItem) * std::max<int64_t>((int64_t)tb_items.size(), 1));
+  const int64_t o_tbr = ar.reserve(8 * std::max<int64_t>((int64_t)tb_row.size(), 1));
   auto build = [&](char* base) {
     ar.base = base;
     runS = Run<double>();
@@ -1239,8 +1280,8 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     TW* winbase = reinterpret_cast<TW*>(f.ptr<char>(f.o_win));
     if (!var) return;
     for (int ci = 0; ci < nch; ++ci) {
-      predict_windows<TW>(f, runsW[ci], n_u, ubp, Us, VtU, at<TW>(ar, o_X), Xoff, winbase, Xs, Vt, c, f.chunk[ci],
-                          f.chunk[ci + 1], stream);
+      predict_windows<TW>(f, runsW[ci], n_u, ubp, Us, VtU, at<TW>(ar, o_X), Xoff, winbase, Xs, Vt, c, pchunk[ci],
+                          pchunk[ci + 1], stream, use_tband);
       runsW[ci].schedule();
     }
     // G accumulation: window m contributes to test blocks q = m..m+B (delta = q - m)
@@ -1375,15 +1416,24 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   HIPCHK(hipMemcpyAsync(at<char>(ar, o_Xoff), Xoff_h.data(), 8 * M, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(at<char>(ar, o_Tm), f.Tm.data(), 4 * M, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(at<char>(ar, o_twm), f.twm.data(), 4 * M, hipMemcpyHostToDevice, st));
+  if (use_tband) {
+    HIPCHK(hipMemcpyAsync(at<char>(ar, o_tbi), tb_items.data(), sizeof(BandItem) * tb_items.size(),
+                          hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(at<char>(ar, o_tbr), tb_row.data(), 8 * tb_row.size(), hipMemcpyHostToDevice, st));
+  }
   int32_t* stat = at<int32_t>(ar, o_stat);
   double* ldg = at<double>(ar, o_ld);
   HIPCHK(hipMemsetAsync(stat, 0, 4 * (M + 2), st));
   // scale test inputs
   prof::timed(prof::OTHER, 0.0, st, [&] { launch_scale(U, n_u, (int)d, f.ie, at<double>(ar, o_Us64), nullptr, st); });
   HIPCHK(hipGetLastError());
-  auto exec = [&](auto& run, auto* invdiag, int vlen, bool factor = false) {
+  auto exec = [&](auto& run, auto* invdiag, int vlen, bool factor = false, bool with_tband = false) {
     using TT = typename std::remove_pointer<decltype(invdiag)>::type;
     StepArgs<TT> a{};
+    if (with_tband) {
+      a.band = at<TT>(ar, o_tb);
+      a.brow = at<int64_t>(ar, o_tbr);
+    }
     a.rt = run.d_rt;
     a.pd = run.d_pd;
     a.vlen = vlen;
@@ -1459,8 +1509,29 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     HIPCHK(hipGetLastError());
   };
   TW* invs = reinterpret_cast<TW*>(f.ptr<char>(f.o_win_inv));
+  if (use_tband) {
+    BandArgs<TW> ba{};
+    ba.items = at<BandItem>(ar, o_tbi);
+    ba.nitems = (int32_t)tb_items.size();
+    ba.d = (int)d;
+    ba.vlen = (int)sp;
+    ba.noise = 0;  // test and training points are different sets: no noise term
+    ba.vld = sp;
+    ba.Vt = f.ptr<double>(f.o_Vt64);
+    ba.Xs = f.ptr<double>(f.o_Xs64);
+    ba.Vr = at<double>(ar, o_VtU64);
+    ba.Xr = at<double>(ar, o_Us64);
+    ba.sf2 = f.sf2;
+    ba.sn2 = f.sn2;
+    ba.band = at<TW>(ar, o_tb);
+    double fl = 0.0;
+    if (prof::on)
+      for (const BandItem& it : tb_items) fl += 2.0 * it.nr * it.nc * (double)f.s;
+    prof::timed(prof::GEMM, fl, st, [&] { launch_band<TW>(ba, st); });
+    HIPCHK(hipGetLastError());
+  }
   if (!stream) {
-    exec(runsW[0], invs, (int)sp);
+    exec(runsW[0], invs, (int)sp, false, use_tband);
     for (int dl = 0; dl <= f.B; ++dl) g_launch(dl_split[dl], dl_split[dl + 1]);
     xi_launch(0, M, false);
   } else {

@@ -195,7 +195,7 @@ struct Run {
       const ProbDesc& p = pd[it.p];
       const RowTile<T>& ri = rt[p.first + it.tile];
       const RowTile<T>& rj = rt[p.first + j];
-      const double Kv = (ri.vt64 && rj.vt64 && ri.src != SRC_BAND) ? (double)s_valid : 0.0;
+      const double Kv = (ri.vt64 && rj.vt64 && ri.src != SRC_BAND && ri.src != SRC_TBAND) ? (double)s_valid : 0.0;
       const double K = Kv + (double)(cum_nvalid[p.first + j] - cum_nvalid[p.first + std::min(ri.kbeg, j)]);
       const double rows = ri.nvalid, cols = rj.nvalid;
       const double pairs = (ri.is_j && it.tile == j) ? rows * (rows + 1) / 2 : rows * cols;
@@ -420,10 +420,8 @@ void add_window_jtiles(std::vector<RowTile<T>>& rt, const WinGeom& g, T* base, c
                                 f64 ? reinterpret_cast<const T*>(Xs + pt * d) : nullptr, c + pt, nv, TB, SRC_KERNEL, 1);
     t.vt64 = Vt + pt * sp;
     t.xs64 = Xs + pt * d;
-    if (band) {
-      t.src = SRC_BAND;
-      t.pt0 = pt;
-    }
+    t.pt0 = pt;
+    if (band) t.src = SRC_BAND;
     rt.push_back(t);
   }
 }
