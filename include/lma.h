@@ -100,7 +100,11 @@ lma_status lma_fit(const lma_problem *p, hipStream_t stream, lma_state **out);
  * same M blocks: test block q = rows u_block_ptr[q] .. u_block_ptr[q+1]-1
  * (empty blocks allowed).  mean[i] is the predictive mean, var[i] (if var is
  * not NULL) the predictive variance of the noisy output (diagonal of
- * Sigma^LMA_UU).  Errors: LMA_E_ARG, LMA_E_HIP, LMA_E_NOMEM.
+ * Sigma^LMA_UU), returned as Eq. (4) defines it, without clamping: it never
+ * exceeds sigma_s^2 + sigma_n^2, and for 0 < B < M-1 it can be negative at a
+ * few test points, because the covariance of Eq. (2) over training and test
+ * inputs together need not be positive definite there.
+ * Errors: LMA_E_ARG, LMA_E_HIP, LMA_E_NOMEM.
  */
 lma_status lma_predict(lma_state *f, int64_t n_u, const double *U, const int64_t *u_block_ptr,
                        double *mean, double *var, hipStream_t stream);

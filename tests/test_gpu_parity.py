@@ -65,6 +65,25 @@ def test_config0(lib, precision):
     check(lib, synth.make_config(0), precision)
 
 
+def test_wide_windows_and_negative_variances(lib):
+    """n=16384 in [0,1]^8, M=16 k-means blocks of 1024, |S|=64, B=4: windows of
+    5120 points (40 tiles), test points appended to five windows each.  At this
+    order the predictive variance of Eq. (4) is negative for a few test points
+    (the covariance over training and test points is indefinite between
+    B = 0 and B = M - 1); the GPU reports the same values, with the same signs
+    wherever the oracle's value is clear of zero."""
+    p = synth.make_uniform_kmeans(1, 16384, 8, 16, 4, 64, 4096, 0.05, name="wide")
+    order = np.random.default_rng(20150125).permutation(p.n)
+    p = p.with_(S=p.X[np.sort(order[:64])].copy())
+    ref = olma.fit_predict(p)
+    assert np.sum(ref["var"] < 0) >= 1
+    for precision in ("fp64", "mixed"):
+        check(lib, p, precision, ref)
+    _, v, _ = gpu_fit_predict(lib, p, "fp64")
+    clear = np.abs(ref["var"]) > 1e-6
+    assert np.array_equal(v[clear] < 0, ref["var"][clear] < 0)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_band_and_on_the_fly_entries_agree(lib, monkeypatch, precision):
     """Windows that read their residual entries from the shared band (the

@@ -209,10 +209,44 @@ def test_window_form_with_support_off_data_and_d4():
 
 
 def test_variance_below_prior_and_positive():
+    """A well-separated case: every variance lies between the noise and the
+    prior variance (the upper bound holds always, see below)."""
     p = tiny(37).with_(B=1)
     r = lma.fit_predict(p)
     sf2, sn2 = np.exp(p.log_hyp[-2]), np.exp(p.log_hyp[-1])
     assert np.all(r["var"] > sn2 * (1 - 1e-9)) and np.all(r["var"] <= sf2 + sn2 + 1e-12)
+
+
+def negvar_case(B):
+    return synth.make_random(seed=3, n=600, d=3, M=8, s=6, n_u=300, B=B, uneven=(50, 100),
+                             ell_range=(0.1, 0.4), sn2=0.01, name="negvar")
+
+
+@pytest.mark.parametrize("B", [1, 2])
+def test_variance_can_be_negative_between_the_limits(B):
+    """Eq. (1) completes the residual over V = D u U with conditioning sets of
+    training blocks only, so a test point keeps its exact residual covariance
+    with the blocks B before and B after its own while those two blocks are
+    joined only through the Markov approximation.  Sigma_bar_DD stays positive
+    definite (Theorem 1), so Eq. (4) never exceeds the prior variance, but
+    Sigma_bar_VV can be indefinite for 0 < B < M - 1 and then some predictive
+    variances of Eq. (4) are negative.  The window form gives the same values;
+    at B = 0 (PIC) and B = M - 1 (full GP) the same inputs give a positive
+    definite Sigma_bar_VV and positive variances."""
+    p = negvar_case(B)
+    D = dense.Dense(p)
+    m0, v0 = D.predict()
+    assert np.linalg.eigvalsh(D.Sbar[:p.n, :p.n]).min() > 0
+    assert np.linalg.eigvalsh(D.Sbar).min() < 0
+    assert np.sum(v0 < 0) >= 1
+    sf2, sn2 = np.exp(p.log_hyp[-2]), np.exp(p.log_hyp[-1])
+    assert np.all(v0 <= sf2 + sn2 + 1e-12)
+    r = lma.fit_predict(p)
+    assert np.max(np.abs(r["var"] - v0)) < 1e-12 and rel(r["mean"], m0) < 1e-12
+    for Bl in (0, p.M - 1):
+        Dl = dense.Dense(negvar_case(Bl))
+        assert np.linalg.eigvalsh(Dl.Sbar).min() > 0
+        assert np.all(Dl.predict()[1] > 0)
 
 
 # --- gradient ---------------------------------------------------------------
