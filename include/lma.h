@@ -34,7 +34,9 @@ typedef enum {
   LMA_E_ARG = 1,     /* invalid argument (shape, pointer, partition) */
   LMA_E_NOT_PD = 2,  /* a covariance that must be positive definite is not */
   LMA_E_HIP = 3,     /* HIP runtime error */
-  LMA_E_NOMEM = 4    /* device memory for the state could not be allocated */
+  LMA_E_NOMEM = 4,   /* device memory for the state could not be allocated */
+  LMA_E_INTERNAL = 5 /* any other failure inside the library (message in
+                        lma_last_error); no exception ever leaves an entry point */
 } lma_status;
 
 typedef enum {

@@ -19,7 +19,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblma.so")
 
-LMA_OK, LMA_E_ARG, LMA_E_NOT_PD, LMA_E_HIP, LMA_E_NOMEM = 0, 1, 2, 3, 4
+LMA_OK, LMA_E_ARG, LMA_E_NOT_PD, LMA_E_HIP, LMA_E_NOMEM, LMA_E_INTERNAL = 0, 1, 2, 3, 4, 5
 PRECISION = {"fp64": 0, "mixed": 1}
 EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml", "lma_state_bytes", "lma_state_chunks",
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",

@@ -546,6 +546,9 @@ lma_status guard(F&& f) {
   } catch (const std::bad_alloc&) {
     lmart::set_last_error("host allocation failed");
     return LMA_E_NOMEM;
+  } catch (const std::exception& e) {
+    lmart::set_last_error(std::string("internal error: ") + e.what());
+    return LMA_E_INTERNAL;
   }
 }
 

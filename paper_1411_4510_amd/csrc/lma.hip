@@ -1592,6 +1592,9 @@ lma_status lma_fit(const lma_problem* p, hipStream_t stream, lma_state** out) {
   } catch (const std::bad_alloc&) {
     g_err = "host allocation failed";
     return LMA_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = std::string("internal error: ") + e.what();
+    return LMA_E_INTERNAL;
   }
 }
 
@@ -1618,6 +1621,9 @@ lma_status lma_predict(lma_state* f, int64_t n_u, const double* U, const int64_t
   } catch (const std::bad_alloc&) {
     g_err = "host allocation failed";
     return LMA_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = std::string("internal error: ") + e.what();
+    return LMA_E_INTERNAL;
   }
 }
 
@@ -1647,6 +1653,9 @@ lma_status lma_lml(const lma_problem* p, double* lml, double* grad, hipStream_t 
   } catch (const std::bad_alloc&) {
     g_err = "host allocation failed";
     return LMA_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = std::string("internal error: ") + e.what();
+    return LMA_E_INTERNAL;
   }
 }
 
