@@ -65,6 +65,32 @@ def test_config0(lib, precision):
     check(lib, synth.make_config(0), precision)
 
 
+DEGENERATE = {
+    # one block: one window with an empty W_0 (LMA = PIC = the full GP); B is clamped to M - 1
+    "one_block": dict(seed=21, n=150, d=3, M=1, s=20, n_u=30, B=0, uneven=(150, 150)),
+    "one_block_B3": dict(seed=21, n=150, d=3, M=1, s=20, n_u=30, B=3, uneven=(150, 150)),
+    # blocks of a single point, and of one or two points, with empty test blocks
+    "single_point_blocks": dict(seed=22, n=12, d=2, M=12, s=4, n_u=10, B=2, uneven=(1, 1)),
+    "one_or_two_point_blocks": dict(seed=23, n=30, d=2, M=20, s=5, n_u=15, B=3, uneven=(1, 2)),
+    # a support set of one point
+    "support_of_one": dict(seed=24, n=300, d=2, M=4, s=1, n_u=40, B=1, uneven=(50, 100)),
+    # smallest and largest input dimension
+    "d1": dict(seed=25, n=300, d=1, M=5, s=10, n_u=50, B=2, uneven=(40, 80)),
+    "d64": dict(seed=26, n=400, d=64, M=4, s=30, n_u=60, B=1, uneven=(80, 120), ell_range=(3.0, 8.0)),
+    # B beyond M - 1 (clamped: the full GP)
+    "B_beyond_M": dict(seed=27, n=300, d=2, M=4, s=12, n_u=40, B=9, uneven=(50, 100)),
+}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(DEGENERATE))
+def test_degenerate_shapes(lib, name, precision):
+    """Degenerate shapes of the method: a single block, blocks of one point,
+    |S| = 1, d = 1 and d = 64 (the largest supported), B >= M."""
+    p = synth.make_random(name=name, **DEGENERATE[name])
+    check(lib, p, precision)
+
+
 def test_wide_windows_and_negative_variances(lib):
     """n=16384 in [0,1]^8, M=16 k-means blocks of 1024, |S|=64, B=4: windows of
     5120 points (40 tiles), test points appended to five windows each.  At this
