@@ -51,6 +51,30 @@ def test_grad_matches_oracle(lib, ci, prec):
     assert eg <= TOL_GRAD[prec]
 
 
+DEGENERATE = {
+    "one_block": dict(seed=21, n=150, d=3, M=1, s=20, B=0, uneven=(150, 150)),
+    "single_point_blocks": dict(seed=22, n=12, d=2, M=12, s=4, B=2, uneven=(1, 1)),
+    "support_of_one": dict(seed=24, n=300, d=2, M=4, s=1, B=1, uneven=(50, 100)),
+    "d1": dict(seed=25, n=300, d=1, M=5, s=10, B=2, uneven=(40, 80)),
+    "d64": dict(seed=26, n=400, d=64, M=4, s=30, B=1, uneven=(80, 120), ell_range=(3.0, 8.0)),
+    "B_beyond_M": dict(seed=27, n=300, d=2, M=4, s=12, B=9, uneven=(50, 100)),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", list(DEGENERATE))
+def test_grad_degenerate_shapes(lib, name, prec):
+    """The adjoint at a single block, blocks of one point, |S| = 1, d = 1,
+    d = 64 (66 gradient entries) and B >= M."""
+    p = problem(DEGENERATE[name])
+    print(f"case {name} {prec}", flush=True)
+    lv, go = olma.lml_grad(p)
+    l, g = lib.lml(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp, p.prior_mean, precision=prec, grad=True)
+    eg, el = rel(g, go), abs(l - lv) / abs(lv)
+    print(f"  rel err grad {eg:.2e} lml {el:.2e}", flush=True)
+    assert el <= TOL[prec] and eg <= TOL_GRAD[prec]
+
+
 def test_grad_central_differences(lib):
     """Central differences of the GPU likelihood, step 1e-5 in each log-hyperparameter."""
     p = problem(CASES[4])

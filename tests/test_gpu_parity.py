@@ -91,6 +91,23 @@ def test_degenerate_shapes(lib, name, precision):
     check(lib, p, precision)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_mean_only_prediction(lib, precision):
+    """lma_predict with var = NULL: the mean alone, equal to the mean of the
+    full call and within the bar of the oracle's."""
+    p = synth.make_random(seed=29, n=1500, d=3, M=6, s=60, n_u=200, B=2, uneven=(150, 350),
+                          empty_test_block=4, name="mean_only")
+    ref = olma.fit_predict(p)
+    st = lib.fit_problem(p, precision=precision)
+    m_only, v_none = st.predict(p.U, p.u_block_ptr, want_var=False)
+    m_full, _ = st.predict(p.U, p.u_block_ptr)
+    st.free()
+    assert v_none is None
+    m_only, m_full = m_only.cpu().numpy(), m_full.cpu().numpy()
+    assert rel(m_only, ref["mean"]) <= TOL[precision]
+    assert np.max(np.abs(m_only - m_full)) <= 1e-12 * np.max(np.abs(m_full))
+
+
 def test_wide_windows_and_negative_variances(lib):
     """n=16384 in [0,1]^8, M=16 k-means blocks of 1024, |S|=64, B=4: windows of
     5120 points (40 tiles), test points appended to five windows each.  At this
