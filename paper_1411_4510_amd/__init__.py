@@ -24,6 +24,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml", "lma_state_bytes", "lma_state_chunks",
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
            "lma_profile_read", "lma_release_cache")
+PART_EXPORTS = ("lma_kmeans_assign", "lma_kmeans_update", "lma_kmeans")
 DS_EXPORTS = ("lma_ds_create", "lma_ds_free", "lma_ds_set_params", "lma_ds_get_params", "lma_ds_features",
               "lma_ds_forward", "lma_ds_backward", "lma_ds_adam")
 
@@ -120,6 +121,13 @@ def load(path: str = LIB_PATH):
     lib.lma_ds_backward.restype = st
     lib.lma_ds_adam.argtypes = [vp, f32, f32, f32, f32, vp]
     lib.lma_ds_adam.restype = st
+    i32 = ctypes.c_int32
+    lib.lma_kmeans_assign.argtypes = [vp, i64, i32, vp, i32, vp, vp, vp]
+    lib.lma_kmeans_assign.restype = st
+    lib.lma_kmeans_update.argtypes = [vp, i64, i32, vp, i32, vp, vp, vp]
+    lib.lma_kmeans_update.restype = st
+    lib.lma_kmeans.argtypes = [vp, i64, i32, vp, i32, i32, vp, vp, vp]
+    lib.lma_kmeans.restype = st
     _lib = lib
     return lib
 
@@ -325,6 +333,51 @@ def release_cache():
     """Free the device memory the library keeps for reuse between calls."""
     load()
     _lib.lma_release_cache()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def kmeans_assign(P, C, want_dist=True, stream=None):
+    """Nearest centre of each point (include/lma_part.h): (label int32 [n],
+    squared distance float64 [n] or None) as device tensors."""
+    import torch
+    load()
+    Pd, Cd = _dev(P, torch), _dev(C, torch)
+    n, d = Pd.shape
+    label = torch.empty(n, dtype=torch.int32, device="cuda")
+    dist2 = torch.empty(n, dtype=torch.float64, device="cuda") if want_dist else None
+    _check(_lib.lma_kmeans_assign(_ptr(Pd), n, d, _ptr(Cd), Cd.shape[0], _ptr(label), _ptr(dist2),
+                                  _stream(torch, stream)))
+    return label, dist2
+
+
+def kmeans_update(P, label, C, stream=None):
+    """Centre update of Lloyd's iteration: (new centres [k, d], counts int64 [k])."""
+    import torch
+    load()
+    Pd = _dev(P, torch)
+    Cd = _dev(C, torch).clone()
+    lab = torch.as_tensor(label, device="cuda").to(torch.int32).contiguous()
+    count = torch.empty(Cd.shape[0], dtype=torch.int64, device="cuda")
+    _check(_lib.lma_kmeans_update(_ptr(Pd), Pd.shape[0], Pd.shape[1], _ptr(lab), Cd.shape[0], _ptr(Cd),
+                                  _ptr(count), _stream(torch, stream)))
+    return Cd, count
+
+
+def kmeans(P, C0, iters, stream=None):
+    """Lloyd's iteration from centres C0: (centres, label, squared distance)."""
+    import torch
+    load()
+    Pd = _dev(P, torch)
+    Cd = _dev(C0, torch).clone()
+    n = Pd.shape[0]
+    label = torch.empty(n, dtype=torch.int32, device="cuda")
+    dist2 = torch.empty(n, dtype=torch.float64, device="cuda")
+    _check(_lib.lma_kmeans(_ptr(Pd), n, Pd.shape[1], _ptr(Cd), Cd.shape[0], int(iters), _ptr(label), _ptr(dist2),
+                           _stream(torch, stream)))
+    return Cd, label, dist2
 
 
 def version():

@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblma.so")
-SOURCES = ["engine.hip", "kernels_misc.hip", "vecsolve.hip", "grad.hip", "kvec.hip", "lma.hip", "lma_grad.hip", "ds.hip"]
+SOURCES = ["engine.hip", "kernels_misc.hip", "vecsolve.hip", "grad.hip", "kvec.hip", "lma.hip", "lma_grad.hip", "ds.hip",
+           "kmeans.hip"]
 ARCH = os.environ.get("LMA_OFFLOAD_ARCH", "gfx950")
 
 

@@ -23,6 +23,7 @@ def test_header_declares_the_boundary():
         assert n in names
     assert set(names) == set(lma.EXPORTS)
     assert set(header_functions("lma_ds.h")) == set(lma.DS_EXPORTS)
+    assert set(header_functions("lma_part.h")) == set(lma.PART_EXPORTS)
 
 
 @pytest.fixture(scope="module")
@@ -33,7 +34,7 @@ def so():
 
 
 def test_library_exports_every_declared_symbol(so):
-    for name in header_functions() + header_functions("lma_ds.h"):
+    for name in header_functions() + header_functions("lma_ds.h") + header_functions("lma_part.h"):
         assert hasattr(so, name), name
 
 
@@ -106,3 +107,32 @@ def test_profile_struct_matches_header_layout():
     names = [f for f, _ in lma.Profile._fields_]
     assert names[:8] == ["update_ms", "diag_ms", "trsm_ms", "other_ms", "update_alg_flops",
                          "update_alg_flops_f64", "update_launches", "other_launches"]
+
+
+KMEANS_BAD = [
+    ("d = 0", dict(d=0)),
+    ("d = 65", dict(d=65)),
+    ("k = 0", dict(k=0)),
+    ("k beyond 65536", dict(k=65537)),
+    ("n < 0", dict(n=-1)),
+    ("NULL points", dict(P=None)),
+    ("NULL centres", dict(C=None)),
+    ("NULL labels", dict(label=None)),
+    ("iters < 0", dict(iters=-1)),
+]
+
+
+@pytest.mark.parametrize("what,kw", KMEANS_BAD, ids=[w for w, _ in KMEANS_BAD])
+def test_kmeans_argument_errors_without_gpu(so, what, kw):
+    """The k-means entry points reject bad shapes and NULL arrays on the host
+    (no device call is made for them)."""
+    vp = ctypes.c_void_p
+    so.lma_kmeans.argtypes = [vp, ctypes.c_int64, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp]
+    so.lma_kmeans.restype = ctypes.c_int
+    so.lma_last_error.restype = ctypes.c_char_p
+    dummy = vp(0x1000)  # never dereferenced: every case fails its host check first
+    a = dict(P=dummy, n=10, d=2, C=dummy, k=3, iters=1, label=dummy)
+    a.update(kw)
+    st = so.lma_kmeans(a["P"], a["n"], a["d"], a["C"], a["k"], a["iters"], a["label"], None, None)
+    assert st == lma.LMA_E_ARG, what
+    assert so.lma_last_error().decode()
