@@ -17,9 +17,11 @@
  *     float64 (no fused multiply-add);
  *   - nearest centre: the smallest distance, ties to the lowest centre index;
  *     a point whose distances are all NaN gets centre 0 and distance +inf;
- *   - centre update: the float64 sum of the assigned points' coordinates in
- *     increasing point index, then one division by their count; a centre with
- *     no assigned point keeps its coordinates.
+ *   - centre update: the points are cut into chunks of 4096 consecutive
+ *     indices; per chunk the coordinates of a centre's points are summed in
+ *     increasing index from 0, the chunk sums (0 for a chunk without its
+ *     points) are added in chunk order from 0, then one division by the
+ *     count; a centre with no assigned point keeps its coordinates.
  *
  * Conventions as in lma.h: DEVICE pointers unless marked (host), row-major,
  * caller-owned buffers, work ordered on the given stream, status codes with
@@ -48,8 +50,10 @@ lma_status lma_kmeans_assign(const double *P, int64_t n, int32_t d, const double
 /*
  * Centre update: C [k][d] (in/out) becomes the mean of the points with each
  * label; count [k] (or NULL) receives the number of points per centre.  A
- * point whose label lies outside 0..k-1 counts for no centre.
- * Errors: LMA_E_ARG, LMA_E_HIP.
+ * point whose label lies outside 0..k-1 counts for no centre.  Uses a
+ * transient device block of about 8*k*(d+1) bytes per 4096 points (at most
+ * 1 GiB at once) and synchronises the stream before returning it.
+ * Errors: LMA_E_ARG, LMA_E_HIP, LMA_E_NOMEM.
  */
 lma_status lma_kmeans_update(const double *P, int64_t n, int32_t d, const int32_t *label, int32_t k, double *C,
                              int64_t *count, hipStream_t stream);
@@ -57,8 +61,9 @@ lma_status lma_kmeans_update(const double *P, int64_t n, int32_t d, const int32_
 /*
  * Lloyd's iteration: iters rounds of (assign, update) starting from the
  * centres in C (in/out), then a final assignment into label [n] (and dist2
- * [n] or NULL) against the final centres.  iters >= 0.
- * Errors: LMA_E_ARG, LMA_E_HIP.
+ * [n] or NULL) against the final centres.  iters >= 0.  Synchronises the
+ * stream once per round (the centre update).
+ * Errors: LMA_E_ARG, LMA_E_HIP, LMA_E_NOMEM.
  */
 lma_status lma_kmeans(const double *P, int64_t n, int32_t d, double *C, int32_t k, int32_t iters, int32_t *label,
                       double *dist2, hipStream_t stream);

@@ -11,13 +11,15 @@ that the library's C ABI fixes:
   nearest centre    the smallest distance, ties to the lowest centre index
                     (a point whose distances are all NaN keeps centre 0 and
                     distance +inf);
-  centre update     the sum, in increasing point index and starting from 0, of
-                    the coordinates of the points with that label, divided
-                    once by their count; a centre without points keeps its
-                    coordinates.
+  centre update     the points are cut into chunks of 4096 consecutive
+                    indices; per chunk, the coordinates of the points with that
+                    label are summed in increasing index starting from 0; the
+                    chunk sums (0 for a chunk without such points) are added in
+                    chunk order starting from 0; one division by the count; a
+                    centre without points keeps its coordinates.
 
 numpy evaluates every elementwise operation below with one rounding and no
-fused multiply-add, and cumsum adds in index order.
+fused multiply-add, and cumsum adds in index order (along the given axis).
 """
 import numpy as np
 
@@ -45,19 +47,29 @@ def assign(P, C):
     return arg, best
 
 
+CHUNK = 4096
+
+
 def update(P, label, C):
-    """New centres (mean of each label's points) and the count per centre."""
+    """New centres (mean of each label's points, summed in chunk order) and the
+    count per centre."""
     P, C = np.asarray(P, dtype=np.float64), np.array(C, dtype=np.float64)
     label = np.asarray(label)
+    n, d = P.shape
+    nch = -(-n // CHUNK)
     count = np.zeros(C.shape[0], dtype=np.int64)
     for c in range(C.shape[0]):
         idx = np.flatnonzero(label == c)
         count[c] = idx.size
         if idx.size == 0:
             continue
-        for t in range(P.shape[1]):
-            s = np.cumsum(np.r_[0.0, P[idx, t]])[-1]
-            C[c, t] = s / float(idx.size)
+        chunk_sums = np.zeros((nch, d))
+        ch = idx // CHUNK
+        for g in np.unique(ch):
+            rows = P[idx[ch == g]]
+            chunk_sums[g] = np.cumsum(np.vstack([np.zeros((1, d)), rows]), axis=0)[-1]
+        total = np.cumsum(np.vstack([np.zeros((1, d)), chunk_sums]), axis=0)[-1]
+        C[c] = total / float(idx.size)
     return C, count
 
 

@@ -8,13 +8,18 @@
 // sums (contraction into fused multiply-adds is switched off), so the result
 // is the same bit for bit as any plain evaluation in that order.
 //
-// Centre update: one thread per (centre, coordinate) walks all points in
-// increasing index and adds the coordinate of those with its label (the label
-// read is wave-uniform), then divides once by the count.  Every sum has a
-// fixed order, so the update does not depend on scheduling.
+// Centre update: the points are cut into chunks of 4096 consecutive indices.
+// One thread per (chunk, centre, coordinate) walks its chunk in increasing
+// index and adds the coordinate of the points with its label (the label read
+// is wave-uniform); a second kernel adds the chunk sums in chunk order and
+// divides once by the count.  Every sum has a fixed order, so the update does
+// not depend on scheduling, and the walk spreads over chunks x centres x
+// coordinates threads (10752 waves at n=524288, k=256, d=21).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 
 #include "lma_part.h"
 #include "misc.h"
@@ -27,6 +32,8 @@ constexpr int NTA = 256;   // threads per workgroup, assignment
 constexpr int CG = 8;      // centres per pass
 constexpr int NTU = 64;    // threads per workgroup, update
 constexpr int MAX_K = 65536;
+constexpr int64_t CHUNK = 4096;         // points per partial sum of the update
+constexpr int64_t PART_BYTES = 1ll << 30;  // partial sums held at once
 
 __global__ __launch_bounds__(NTA) void k_km_assign(const double* __restrict__ P, int64_t n, int d,
                                                    const double* __restrict__ C, int k, int32_t* __restrict__ label,
@@ -65,16 +72,22 @@ __global__ __launch_bounds__(NTA) void k_km_assign(const double* __restrict__ P,
   if (dist2) dist2[i] = best;
 }
 
-__global__ __launch_bounds__(NTU) void k_km_update(const double* __restrict__ P, int64_t n, int d,
-                                                   const int32_t* __restrict__ label, int k, double* __restrict__ C,
-                                                   int64_t* __restrict__ count) {
-  const int64_t e = (int64_t)blockIdx.x * NTU + threadIdx.x;
-  if (e >= (int64_t)k * d) return;
+__global__ __launch_bounds__(NTU) void k_km_partial(const double* __restrict__ P, int64_t n, int d,
+                                                    const int32_t* __restrict__ label, int k, int64_t ch0,
+                                                    int64_t nbx, double* __restrict__ part,
+                                                    int64_t* __restrict__ pcnt) {
+  // block b covers chunk ch0 + b / nbx and threads (b % nbx) * NTU + tid of the k*d (centre, coordinate) pairs
+  const int64_t kd = (int64_t)k * d;
+  const int64_t g = blockIdx.x / nbx;
+  const int64_t e = (blockIdx.x - g * nbx) * NTU + threadIdx.x;
+  if (e >= kd) return;
   const int c = (int)(e / d), t = (int)(e - (int64_t)c * d);
+  const int64_t i0 = (ch0 + g) * CHUNK;
+  const int64_t i1 = i0 + CHUNK < n ? i0 + CHUNK : n;
   double s = 0.0;
   int64_t cnt = 0;
-  int64_t i = 0;
-  for (; i + 8 <= n; i += 8) {
+  int64_t i = i0;
+  for (; i + 8 <= i1; i += 8) {
     int32_t lb[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) lb[j] = label[i + j];
@@ -85,11 +98,34 @@ __global__ __launch_bounds__(NTU) void k_km_update(const double* __restrict__ P,
         ++cnt;
       }
   }
-  for (; i < n; ++i)
+  for (; i < i1; ++i)
     if (label[i] == c) {
       s = s + P[i * d + t];
       ++cnt;
     }
+  part[g * kd + e] = s;
+  if (t == 0) pcnt[g * k + c] = cnt;
+}
+
+__global__ __launch_bounds__(NTU) void k_km_combine(const double* __restrict__ part, const int64_t* __restrict__ pcnt,
+                                                    int64_t nch, int k, int d, double* __restrict__ srun,
+                                                    int64_t* __restrict__ crun, int first, int last,
+                                                    double* __restrict__ C, int64_t* __restrict__ count) {
+  const int64_t kd = (int64_t)k * d;
+  const int64_t e = (int64_t)blockIdx.x * NTU + threadIdx.x;
+  if (e >= kd) return;
+  const int c = (int)(e / d), t = (int)(e - (int64_t)c * d);
+  double s = first ? 0.0 : srun[e];
+  int64_t cnt = first ? 0 : crun[e];
+  for (int64_t g = 0; g < nch; ++g) {
+    s = s + part[g * kd + e];
+    cnt += pcnt[g * k + c];
+  }
+  if (!last) {
+    srun[e] = s;
+    crun[e] = cnt;
+    return;
+  }
   if (cnt > 0) C[e] = s / (double)cnt;
   if (count && t == 0) count[c] = cnt;
 }
@@ -118,13 +154,48 @@ void assign(const double* P, int64_t n, int32_t d, const double* C, int32_t k, i
   HIPCHK(hipGetLastError());
 }
 
+// Centre update in chunk order.  Chunks are processed in groups whose partial
+// sums fit PART_BYTES; running sums carry the order across groups.  The
+// scratch block comes from the library's device cache and goes back after a
+// stream synchronisation.
 void update(const double* P, int64_t n, int32_t d, const int32_t* label, int32_t k, double* C, int64_t* count,
             hipStream_t st) {
-  const int64_t nt = (int64_t)k * d;
-  const int64_t nb = (nt + lma::part::NTU - 1) / lma::part::NTU;
-  hipLaunchKernelGGL(lma::part::k_km_update, dim3((unsigned)nb), dim3(lma::part::NTU), 0, st, P, n, (int)d, label,
-                     (int)k, C, count);
-  HIPCHK(hipGetLastError());
+  using namespace lma::part;
+  const int64_t kd = (int64_t)k * d;
+  const int64_t nch = n > 0 ? (n + CHUNK - 1) / CHUNK : 0;
+  const int64_t per = (int64_t)sizeof(double) * kd + (int64_t)sizeof(int64_t) * k;
+  int64_t cap = PART_BYTES;
+  if (const char* env = std::getenv("LMA_KMEANS_PART_BYTES")) cap = std::max<long long>(1, std::atoll(env));
+  const int64_t group = nch == 0 ? 0 : std::max<int64_t>(1, std::min<int64_t>(nch, cap / per));
+  const int64_t nbx = (kd + NTU - 1) / NTU;
+  if (group * nbx > 0x7fffffff) throw Err{LMA_E_ARG, "too many centres x coordinates for one launch"};
+  const size_t bytes = (size_t)(group * per + kd * (int64_t)(sizeof(double) + sizeof(int64_t)));
+  char* mem = static_cast<char*>(lmart::devcache::get(bytes));
+  if (!mem) throw Err{LMA_E_NOMEM, "device allocation for the centre update failed"};
+  double* part = reinterpret_cast<double*>(mem);
+  int64_t* pcnt = reinterpret_cast<int64_t*>(mem + sizeof(double) * group * kd);
+  double* srun = reinterpret_cast<double*>(mem + group * per);
+  int64_t* crun = reinterpret_cast<int64_t*>(mem + group * per + sizeof(double) * kd);
+  hipError_t err = hipSuccess;
+  if (nch == 0) {
+    hipLaunchKernelGGL(k_km_combine, dim3((unsigned)nbx), dim3(NTU), 0, st, part, pcnt, (int64_t)0, (int)k, (int)d,
+                       srun, crun, 1, 1, C, count);
+    err = hipGetLastError();
+  }
+  for (int64_t ch0 = 0; ch0 < nch && err == hipSuccess; ch0 += group) {
+    const int64_t ng = std::min<int64_t>(group, nch - ch0);
+    hipLaunchKernelGGL(k_km_partial, dim3((unsigned)(ng * nbx)), dim3(NTU), 0, st, P, n, (int)d, label, (int)k, ch0,
+                       nbx, part, pcnt);
+    err = hipGetLastError();
+    if (err != hipSuccess) break;
+    hipLaunchKernelGGL(k_km_combine, dim3((unsigned)nbx), dim3(NTU), 0, st, part, pcnt, ng, (int)k, (int)d, srun,
+                       crun, ch0 == 0 ? 1 : 0, ch0 + ng >= nch ? 1 : 0, C, count);
+    err = hipGetLastError();
+  }
+  const hipError_t es = hipStreamSynchronize(st);
+  lmart::devcache::put(mem, bytes);
+  if (err != hipSuccess) throw Err{LMA_E_HIP, std::string("k-means update launch: ") + hipGetErrorString(err)};
+  if (es != hipSuccess) throw Err{LMA_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(es)};
 }
 
 template <class F>

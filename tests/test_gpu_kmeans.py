@@ -57,6 +57,21 @@ def test_lloyd_bit_exact(lib, name):
     assert np.array_equal(np_(Cg), Co) and np.array_equal(np_(lg), lo) and np.array_equal(np_(dg), do)
 
 
+def test_update_in_groups_of_chunks(lib, monkeypatch):
+    """Partial sums held for one chunk at a time (LMA_KMEANS_PART_BYTES): the
+    running sums carry the chunk order across groups, so the result is the same
+    bit for bit."""
+    rng = np.random.default_rng(8)
+    P = rng.uniform(0, 1, size=(13000, 3))
+    C = rng.uniform(0, 1, size=(17, 3))
+    lo, _ = okm.assign(P, C)
+    Co, co = okm.update(P, lo, C)
+    monkeypatch.setenv("LMA_KMEANS_PART_BYTES", "1")
+    Cg, cg = lib.kmeans_update(P, lo, C)
+    monkeypatch.delenv("LMA_KMEANS_PART_BYTES")
+    assert np.array_equal(np_(cg), co) and np.array_equal(np_(Cg), Co)
+
+
 def test_workload_shape_sampled(lib):
     """n=524288 points in 21-D from a mixture of 32 Gaussians, k=256 centres
     started at random rows, 10 Lloyd rounds on the GPU.  The oracle then checks
