@@ -135,6 +135,7 @@ def main():
     ap.add_argument("--grad-evals", type=int, default=1, help="timed LML+gradient evaluations per precision")
     ap.add_argument("--no-n131072", action="store_true",
                     help="skip the LML+gradient rate at the n=131072 hyperparameter-fitting workload")
+    ap.add_argument("--no-kmeans", action="store_true", help="skip the partitioner k-means timing")
     ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--small", action="store_true", help="n=65536 workload (quick check)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -265,6 +266,24 @@ def main():
             log(f"n=131072 {prec} LML+grad: " + ", ".join(f"{k}: {v['s_per_eval'] * 1e3:.0f} ms" for k, v in rec.items()))
         del X3, y3, S3
 
+    # partitioner k-means steps on the same points: 10 Lloyd rounds + final
+    # assignment, k = M centres started at seeded rows
+    km = None
+    if not args.no_kmeans:
+        try:
+            C0 = p.X[np.sort(np.random.default_rng(14114510).choice(p.n, p.M, replace=False))]
+            lma.kmeans(X, C0, 1)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            lma.kmeans(X, C0, 10)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            km = {"workload": f"k-means, n={p.n}, d={p.d}, k={p.M}, 10 Lloyd rounds + final assignment",
+                  "s": dt, "ms_per_round": dt / 10 * 1e3}
+            log(f"k-means: {dt * 1e3:.1f} ms")
+        except Exception as e:  # reported, never fatal to the headline measurement
+            km = {"error": str(e)}
+
     f_fit, f_pred = algorithmic_flops(p)
     head = "fp64" if "fp64" in res else list(res)[0]
     prof = res[head]["profile"]
@@ -304,6 +323,7 @@ def main():
         "lml_evals_per_s_fp64": lml_rate,
         "lml_grad": grad_res or None,
         "lml_grad_n131072": grad3,
+        "partition_kmeans": km,
         "alg_flops": {"fit": f_fit, "predict": f_pred},
         "roofline": roofline,
     }
