@@ -68,6 +68,19 @@ lma_status lma_kmeans_update(const double *P, int64_t n, int32_t d, const int32_
 lma_status lma_kmeans(const double *P, int64_t n, int32_t d, double *C, int32_t k, int32_t iters, int32_t *label,
                       double *dist2, hipStream_t stream);
 
+/*
+ * Order of the blocks along the Markov chain (host function, no device work):
+ * LMA couples each block with the next B blocks in the given order, so
+ * neighbouring blocks should be close.  C [k][d] (host) are the block centres;
+ * order [k] (host) receives a permutation of 0..k-1: it starts at the centre
+ * farthest from the mean of the centres (the mean summed over the centres in
+ * index order, then divided by k) and moves each time to the nearest centre
+ * not yet visited.  Distances are evaluated as in the assignment above
+ * (coordinates in order, no fused multiply-add; ties to the lowest index).
+ * 1 <= d <= 64, k >= 1.  Errors: LMA_E_ARG.
+ */
+lma_status lma_chain_order(const double *C, int32_t k, int32_t d, int32_t *order);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,10 @@ that the library's C ABI fixes:
   nearest centre    the smallest distance, ties to the lowest centre index
                     (a point whose distances are all NaN keeps centre 0 and
                     distance +inf);
+  chain order       blocks ordered along the Markov chain: start at the centre
+                    farthest from the centres' mean (summed over the centres in
+                    index order, divided by k), then move to the nearest centre
+                    not yet visited (ties to the lowest index);
   centre update     the points are cut into chunks of 4096 consecutive
                     indices; per chunk, the coordinates of the points with that
                     label are summed in increasing index starting from 0; the
@@ -81,3 +85,23 @@ def lloyd(P, C0, iters):
         C, _ = update(P, label, C)
     label, dist2 = assign(P, C)
     return C, label, dist2
+
+
+def chain_order(C):
+    """Order of the centres along a nearest-neighbour chain from the centre
+    farthest from their mean."""
+    C = np.asarray(C, dtype=np.float64)
+    k = C.shape[0]
+    mean = np.cumsum(np.vstack([np.zeros((1, C.shape[1])), C]), axis=0)[-1] / float(k)
+    far = sqdist_to(C, mean)
+    cur = int(np.argmax(far))        # first index among equal maxima
+    seen = np.zeros(k, dtype=bool)
+    order = [cur]
+    seen[cur] = True
+    for _ in range(k - 1):
+        dd = sqdist_to(C, C[cur])
+        dd[seen] = np.inf
+        cur = int(np.argmin(dd))     # first index among equal minima
+        order.append(cur)
+        seen[cur] = True
+    return np.asarray(order, dtype=np.int32)

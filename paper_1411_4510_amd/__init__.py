@@ -24,7 +24,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml", "lma_state_bytes", "lma_state_chunks",
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
            "lma_profile_read", "lma_release_cache")
-PART_EXPORTS = ("lma_kmeans_assign", "lma_kmeans_update", "lma_kmeans")
+PART_EXPORTS = ("lma_kmeans_assign", "lma_kmeans_update", "lma_kmeans", "lma_chain_order")
 DS_EXPORTS = ("lma_ds_create", "lma_ds_free", "lma_ds_set_params", "lma_ds_get_params", "lma_ds_features",
               "lma_ds_forward", "lma_ds_backward", "lma_ds_adam")
 
@@ -128,6 +128,8 @@ def load(path: str = LIB_PATH):
     lib.lma_kmeans_update.restype = st
     lib.lma_kmeans.argtypes = [vp, i64, i32, vp, i32, i32, vp, vp, vp]
     lib.lma_kmeans.restype = st
+    lib.lma_chain_order.argtypes = [vp, i32, i32, vp]
+    lib.lma_chain_order.restype = st
     _lib = lib
     return lib
 
@@ -378,6 +380,17 @@ def kmeans(P, C0, iters, stream=None):
     _check(_lib.lma_kmeans(_ptr(Pd), n, Pd.shape[1], _ptr(Cd), Cd.shape[0], int(iters), _ptr(label), _ptr(dist2),
                            _stream(torch, stream)))
     return Cd, label, dist2
+
+
+def chain_order(C):
+    """Order of the blocks along the Markov chain from their centres (host
+    numpy [k, d] -> int32 permutation [k]; no device work)."""
+    load()
+    Ch = np.ascontiguousarray(np.asarray(C, dtype=np.float64))
+    order = np.empty(Ch.shape[0], dtype=np.int32)
+    _check(_lib.lma_chain_order(Ch.ctypes.data_as(ctypes.c_void_p), Ch.shape[0], Ch.shape[1],
+                                order.ctypes.data_as(ctypes.c_void_p)))
+    return order
 
 
 def version():

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <vector>
 
 #include "lma_part.h"
 #include "misc.h"
@@ -216,6 +217,51 @@ lma_status guard(F&& f) {
   }
 }
 
+#pragma clang fp contract(off)
+double host_sqdist(const double* a, const double* b, int d) {
+  double acc = 0.0;
+  for (int t = 0; t < d; ++t) {
+    const double df = a[t] - b[t];
+    const double sq = df * df;
+    acc = acc + sq;
+  }
+  return acc;
+}
+
+void chain_order(const double* C, int k, int d, int32_t* order) {
+  std::vector<double> mean(d, 0.0);
+  for (int c = 0; c < k; ++c)
+    for (int t = 0; t < d; ++t) mean[t] = mean[t] + C[(int64_t)c * d + t];
+  for (int t = 0; t < d; ++t) mean[t] = mean[t] / (double)k;
+  int cur = 0;
+  double far = -1.0;
+  for (int c = 0; c < k; ++c) {
+    const double q = host_sqdist(C + (int64_t)c * d, mean.data(), d);
+    if (q > far) {
+      far = q;
+      cur = c;
+    }
+  }
+  std::vector<char> seen(k, 0);
+  order[0] = cur;
+  seen[cur] = 1;
+  for (int step = 1; step < k; ++step) {
+    int nxt = -1;
+    double best = 0.0;
+    for (int c = 0; c < k; ++c) {
+      if (seen[c]) continue;
+      const double q = host_sqdist(C + (int64_t)c * d, C + (int64_t)cur * d, d);
+      if (nxt < 0 || q < best) {
+        best = q;
+        nxt = c;
+      }
+    }
+    order[step] = nxt;
+    seen[nxt] = 1;
+    cur = nxt;
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -249,6 +295,15 @@ lma_status lma_kmeans(const double* P, int64_t n, int32_t d, double* C, int32_t 
       if (n > 0) update(P, n, d, label, k, C, nullptr, stream);
     }
     assign(P, n, d, C, k, label, dist2, stream);
+  });
+}
+
+lma_status lma_chain_order(const double* C, int32_t k, int32_t d, int32_t* order) {
+  return guard([&] {
+    if (d < 1 || d > lma::MAX_D) throw Err{LMA_E_ARG, "need 1 <= d <= 64"};
+    if (k < 1) throw Err{LMA_E_ARG, "need k >= 1"};
+    if (!C || !order) throw Err{LMA_E_ARG, "NULL array"};
+    chain_order(C, k, d, order);
   });
 }
 

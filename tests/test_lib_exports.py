@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1411_4510_amd as lma
@@ -136,3 +137,26 @@ def test_kmeans_argument_errors_without_gpu(so, what, kw):
     st = so.lma_kmeans(a["P"], a["n"], a["d"], a["C"], a["k"], a["iters"], a["label"], None, None)
     assert st == lma.LMA_E_ARG, what
     assert so.lma_last_error().decode()
+
+
+@pytest.mark.parametrize("k,d,seed", [(256, 21, 1), (1, 3, 2), (2, 1, 3), (97, 64, 4)])
+def test_chain_order_matches_oracle_bit_for_bit(k, d, seed):
+    """lma_chain_order is a host function (no device work): the same order as
+    the oracle, including duplicated centres (ties to the lowest index)."""
+    from oracle import kmeans as okm
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0, 1, size=(k, d))
+    if k > 4:
+        C[3] = C[1]
+    assert np.array_equal(lma.chain_order(C), okm.chain_order(C))
+
+
+def test_chain_order_argument_errors(so):
+    so.lma_chain_order.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+    so.lma_chain_order.restype = ctypes.c_int
+    buf = (ctypes.c_double * 8)()
+    out = (ctypes.c_int32 * 4)()
+    assert so.lma_chain_order(buf, 0, 2, out) == lma.LMA_E_ARG
+    assert so.lma_chain_order(buf, 4, 0, out) == lma.LMA_E_ARG
+    assert so.lma_chain_order(None, 4, 2, out) == lma.LMA_E_ARG
+    assert so.lma_chain_order(buf, 4, 2, None) == lma.LMA_E_ARG

@@ -99,3 +99,26 @@ def test_update_over_several_chunks():
             for v in P2[l2 == c, t]:
                 seq = seq + v
             assert C2[c, t] == seq / np.sum(l2 == c)
+
+
+def test_chain_order_on_a_line_and_visits_every_centre():
+    """Centres on a line: the chain starts at the end farther from the mean and
+    walks them in sorted order; random centres: a permutation."""
+    xs = np.array([0.0, 0.5, 0.6, 2.0, 3.1, 3.3, 7.0])
+    perm = np.random.default_rng(2).permutation(xs.size)
+    C = np.c_[xs[perm], 2.0 * xs[perm]]
+    order = okm.chain_order(C)
+    assert np.array_equal(C[order, 0], xs[::-1])     # 7.0 is farthest from the mean 2.5
+    R = np.random.default_rng(4).uniform(size=(50, 5))
+    assert sorted(okm.chain_order(R).tolist()) == list(range(50))
+
+
+def test_chain_order_greedy_step_against_brute_force():
+    rng = np.random.default_rng(6)
+    C = rng.uniform(size=(40, 3))
+    order = okm.chain_order(C)
+    D = np.linalg.norm(C[:, None] - C[None], axis=2)
+    assert order[0] == np.argmax(np.linalg.norm(C - C.mean(0), axis=1))
+    for a, b in zip(order[:-1], order[1:]):
+        rest = [c for c in range(40) if c not in order[:list(order).index(b)]]
+        assert D[a, b] <= D[a, rest].min() * (1 + 1e-12)
