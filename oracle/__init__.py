@@ -17,6 +17,10 @@ Three tiers, all numpy/scipy in float64, sharing no code with the GPU path:
              prediction per test block, the log marginal likelihood through
              the matrix inversion lemma of Eq. (5), and its adjoint.
 
+Beside them: deepsets (the warm-start network with the kernels' bfloat16
+roundings) and kmeans (the partitioner's k-means steps and block chain order,
+in the evaluation order the library fixes).
+
 Readings of the paper the oracle takes (where it is silent):
   * noise is attached by index: sigma_n^2 sits on the diagonal of same-set
     blocks (D with D, U with U, S with S) and never on cross-set blocks, even
@@ -25,6 +29,8 @@ Readings of the paper the oracle takes (where it is silent):
   * the prior mean is one constant mu;
   * D^B_m is the next B blocks, truncated at M; the block order is an input;
   * Theorem 2 is used for every B >= 0 (at B = 0 it reduces to PIC);
-  * only the diagonal of the predictive covariance is returned.
+  * only the diagonal of the predictive covariance is returned, unclamped: it
+    can be negative for 0 < B < M - 1, where Sigma_bar over D and U together
+    is indefinite.
 """
 from . import covariance, dense, summaries, lma  # noqa: F401
