@@ -148,7 +148,12 @@ int64_t lma_state_chunks(const lma_state *f);
 /* Message for the last error on the calling thread ("" if none). */
 const char *lma_last_error(void);
 
-/* Block index of the last LMA_E_NOT_PD on the calling thread. */
+/* Which factor the last lma_fit / lma_predict / lma_lml on the calling thread
+ * failed on with LMA_E_NOT_PD: m (0..M-1) for the window of block m, -1 for
+ * Sigma_SS, -2 for Sigma_ddot_SS.  -3 when that call did not fail on a factor:
+ * it succeeded, failed with another status, or found a non-finite log
+ * marginal likelihood or gradient, which no single block is blamed for.
+ * Every one of those entry points resets it to -3 when it starts. */
 int64_t lma_failed_block(void);
 
 /*

@@ -15,12 +15,12 @@ that the library's C ABI fixes:
                     farthest from the centres' mean (summed over the centres in
                     index order, divided by k), then move to the nearest centre
                     not yet visited (ties to the lowest index);
-  centre update     the points are cut into chunks of 4096 consecutive
-                    indices; per chunk, the coordinates of the points with that
-                    label are summed in increasing index starting from 0; the
-                    chunk sums (0 for a chunk without such points) are added in
-                    chunk order starting from 0; one division by the count; a
-                    centre without points keeps its coordinates.
+  centre update     the mean of the points with that label: their
+                    coordinates summed in increasing point index starting from
+                    0, then one division by the count; a centre without points
+                    keeps its coordinates.  (The library may sum in another
+                    order; its result then differs from this one by rounding
+                    only, within the bound of the summation error.)
 
 numpy evaluates every elementwise operation below with one rounding and no
 fused multiply-add, and cumsum adds in index order (along the given axis).
@@ -51,29 +51,20 @@ def assign(P, C):
     return arg, best
 
 
-CHUNK = 4096
-
-
 def update(P, label, C):
-    """New centres (mean of each label's points, summed in chunk order) and the
-    count per centre."""
+    """New centres (mean of each label's points) and the count per centre."""
     P, C = np.asarray(P, dtype=np.float64), np.array(C, dtype=np.float64)
     label = np.asarray(label)
-    n, d = P.shape
-    nch = -(-n // CHUNK)
+    d = P.shape[1]
     count = np.zeros(C.shape[0], dtype=np.int64)
     for c in range(C.shape[0]):
-        idx = np.flatnonzero(label == c)
-        count[c] = idx.size
-        if idx.size == 0:
+        rows = P[label == c]
+        count[c] = rows.shape[0]
+        if count[c] == 0:
             continue
-        chunk_sums = np.zeros((nch, d))
-        ch = idx // CHUNK
-        for g in np.unique(ch):
-            rows = P[idx[ch == g]]
-            chunk_sums[g] = np.cumsum(np.vstack([np.zeros((1, d)), rows]), axis=0)[-1]
-        total = np.cumsum(np.vstack([np.zeros((1, d)), chunk_sums]), axis=0)[-1]
-        C[c] = total / float(idx.size)
+        # sequential sum in increasing index (cumsum adds in order)
+        total = np.cumsum(np.vstack([np.zeros((1, d)), rows]), axis=0)[-1]
+        C[c] = total / float(count[c])
     return C, count
 
 

@@ -138,6 +138,8 @@ def _check(status):
     if status != LMA_OK:
         msg = _lib.lma_last_error().decode()
         block = int(_lib.lma_failed_block()) if status == LMA_E_NOT_PD else None
+        if block == -3:     # a non-finite likelihood or gradient: no single block
+            block = None
         raise LmaError(status, msg, block)
 
 

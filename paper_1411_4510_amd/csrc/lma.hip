@@ -37,7 +37,7 @@ using namespace lma;
 
 namespace {
 thread_local std::string g_err;
-thread_local int64_t g_failed = 0;
+thread_local int64_t g_failed = -3;  // -3: no block (see lma_failed_block)
 }  // namespace
 
 namespace lmart {
@@ -1579,6 +1579,7 @@ extern "C" {
 
 lma_status lma_fit(const lma_problem* p, hipStream_t stream, lma_state** out) {
   g_err.clear();
+  g_failed = -3;
   if (!out) {
     g_err = "out is NULL";
     return LMA_E_ARG;
@@ -1601,6 +1602,7 @@ lma_status lma_fit(const lma_problem* p, hipStream_t stream, lma_state** out) {
 lma_status lma_predict(lma_state* f, int64_t n_u, const double* U, const int64_t* u_block_ptr, double* mean,
                        double* var, hipStream_t stream) {
   g_err.clear();
+  g_failed = -3;
   try {
     if (!f) throw Err{LMA_E_ARG, "state is NULL"};
     if (n_u < 0) throw Err{LMA_E_ARG, "n_u < 0"};
@@ -1629,6 +1631,7 @@ lma_status lma_predict(lma_state* f, int64_t n_u, const double* U, const int64_t
 
 lma_status lma_lml(const lma_problem* p, double* lml, double* grad, hipStream_t stream) {
   g_err.clear();
+  g_failed = -3;
   if (!lml) {
     g_err = "lml is NULL";
     return LMA_E_ARG;

@@ -237,3 +237,7 @@ def test_non_pd_support_covariance(lib):
     with pytest.raises(lib.LmaError) as e:
         lib.fit(p.X, p.y, p.block_ptr, S, p.B, p.log_hyp)
     assert e.value.status == lib.LMA_E_NOT_PD and e.value.block == -1
+    # the next call that succeeds names no block
+    st = lib.fit(p.X, p.y, p.block_ptr, p.S, p.B, p.log_hyp)
+    st.free()
+    assert lib.load().lma_failed_block() == -3

@@ -51,6 +51,28 @@ def test_version_and_error_without_gpu(so):
     assert "NULL" in so.lma_last_error().decode()
 
 
+def test_failed_block_is_reset_by_every_entry_point(so):
+    """lma_failed_block names no block (-3) after a call that did not fail on a
+    factor: each entry point resets it when it starts."""
+    so.lma_failed_block.restype = ctypes.c_int64
+    so.lma_fit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    so.lma_fit.restype = ctypes.c_int
+    so.lma_predict.restype = ctypes.c_int
+    so.lma_predict.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    so.lma_lml.restype = ctypes.c_int
+    so.lma_lml.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    assert so.lma_failed_block() == -3
+    h = ctypes.c_void_p()
+    assert so.lma_fit(None, None, ctypes.byref(h)) == lma.LMA_E_ARG
+    assert so.lma_failed_block() == -3
+    assert so.lma_predict(None, 1, None, None, None, None, None) == lma.LMA_E_ARG
+    assert so.lma_failed_block() == -3
+    v = ctypes.c_double()
+    assert so.lma_lml(None, ctypes.byref(v), None, None) == lma.LMA_E_ARG
+    assert so.lma_failed_block() == -3
+
+
 BAD_PROBLEMS = [
     ("d = 0", dict(d=0)),
     ("d = 65", dict(d=65)),

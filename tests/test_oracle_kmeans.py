@@ -81,24 +81,22 @@ def test_lloyd_objective_does_not_increase():
         C, _ = okm.update(X, lab, C)
 
 
-def test_update_over_several_chunks():
-    """10000 points (three chunks of 4096): the chunk-ordered sums give the
-    group means within rounding, and with all points in one chunk the result is
-    the plain sequential sum."""
+def test_update_is_the_sequential_sum_in_index_order():
+    """10000 points: each centre is its points' coordinates added one at a time
+    in increasing index from 0, divided once by the count (checked against a
+    plain Python loop for a few coordinates), and equals numpy's group mean
+    within rounding."""
     rng = np.random.default_rng(3)
     P = rng.standard_normal((10000, 3))
     lab = rng.integers(0, 5, 10000)
     C, _ = okm.update(P, lab, np.zeros((5, 3)))
     for c in range(5):
-        assert np.allclose(C[c], P[lab == c].mean(axis=0), rtol=1e-13, atol=1e-15)
-    P2, l2 = P[:3000], lab[:3000]
-    C2, _ = okm.update(P2, l2, np.zeros((5, 3)))
-    for c in range(5):
-        for t in range(3):
-            seq = 0.0
-            for v in P2[l2 == c, t]:
-                seq = seq + v
-            assert C2[c, t] == seq / np.sum(l2 == c)
+        assert np.allclose(C[c], P[lab == c].mean(axis=0), rtol=1e-12, atol=1e-15)
+    for c, t in ((0, 0), (3, 2)):
+        seq = 0.0
+        for v in P[lab == c, t]:
+            seq = seq + float(v)
+        assert C[c, t] == seq / float(np.sum(lab == c))
 
 
 def test_chain_order_on_a_line_and_visits_every_centre():
