@@ -36,6 +36,22 @@ collapse onto the single W_q term.
 All in one pass over windows: window m's triangular solve carries the test
 right-hand sides of blocks q = m .. m+B, and the per-point sums finish once g is
 known.
+
+Full predictive covariance (Eq. (4) beyond its diagonal; predict_cov).  With
+E_u = k_u - G_u, Eq. (4) through the matrix inversion lemma of Eq. (5) is
+  Sigma_uv = R_bar_uv - xi_uv + E_u^T Sigma_ddot_SS^-1 E_v,
+  xi_uv = R_bar_uD R_bar_DD^-1 R_bar_Dv.
+For u in test block q and v in block r with |q - r| <= B, R_bar_uv = R_uv
+(Eq. (1) inside the band; noise on the diagonal) and, with a = min(q, r),
+b = max(q, r),
+  xi_uv = sum_{m=b-B}^{a-1} x^m_u . x^m_v  +  X^a_u . X^a_v,
+where X^a_u is the whole column of L_a^-1 R_{J_a u} (its first |W_a| rows are
+pi_u when a = q): the windows below b-B hold no whitened part of v, and the
+windows above a collapse onto W_a as for the diagonal.  For |q - r| > B, Eq. (1)
+gives R_bar_uv = pi_u . L11(q)^-1 R_bar_{W_q v} (q < r), which is also all of
+xi_uv, so the two cancel and only the low-rank term E_u^T Sigma_ddot^-1 E_v is
+left: given the training outputs, test points more than B blocks apart are
+uncorrelated in the residual.  (Pinned against the dense definition.)
 """
 import numpy as np
 import scipy.linalg as sla
@@ -57,8 +73,10 @@ def window_index(block_ptr, M, B, m):
 class Fit:
     """Fit state: L_SS, V = L_SS^-1 K_SD, the global summary and its solve."""
 
-    def __init__(self, p, windows=None, test=True):
+    def __init__(self, p, windows=None, test=True, keep_test_cols=False):
         self.p = p
+        self.keep = keep_test_cols
+        self.Xcols = {}
         n, d, M = p.n, p.d, p.M
         self.B = min(int(p.B), M - 1)
         self.ell, self.sf2, self.sn2 = unpack(p.log_hyp, d)
@@ -118,6 +136,8 @@ class Fit:
         self.ldR += 2.0 * float(np.sum(np.log(np.diag(L)[w:])))
         for q, uq, off in qs:
             X_ = sol[:, off:off + uq.size]
+            if self.keep:
+                self.Xcols[(m, q)] = (X_.copy(), w)
             x = X_[w:]
             self.G[uq] += x.T @ Z
             self.l_u[uq] += x.T @ z
@@ -148,6 +168,45 @@ class Fit:
         var = (self.sf2 + self.sn2 - np.sum(self.V_U ** 2, axis=0) - self.xi
                + np.sum(T * T, axis=0))
         return mean, var
+
+
+    def predict_cov(self):
+        """Full predictive covariance over the test points (needs a fit made
+        with keep_test_cols=True)."""
+        p, B, M = self.p, self.B, self.p.M
+        ubp = p.u_block_ptr
+        n_u = p.U.shape[0]
+        E = self.K_SU.T - self.G
+        T = sla.solve_triangular(self.L_dd, E.T, lower=True)
+        cov = T.T @ T
+        for q in range(M):
+            uq = np.arange(ubp[q], ubp[q + 1])
+            for r in range(q, min(q + B, M - 1) + 1):
+                vr = np.arange(ubp[r], ubp[r + 1])
+                if uq.size == 0 or vr.size == 0:
+                    continue
+                Rqr = k_cross(p.U[uq], p.U[vr], p.log_hyp) - self.V_U[:, uq].T @ self.V_U[:, vr]
+                if q == r:
+                    Rqr[np.diag_indices_from(Rqr)] += self.sn2
+                xi = np.zeros((uq.size, vr.size))
+                for m in range(max(0, r - B), q):          # D rows of the windows below q
+                    Xu, w = self.Xcols[(m, q)]
+                    Xv, _ = self.Xcols[(m, r)]
+                    xi += Xu[w:].T @ Xv[w:]
+                Xu, _ = self.Xcols[(q, q)]                   # all rows of window q
+                Xv, _ = self.Xcols[(q, r)]
+                xi += Xu.T @ Xv
+                cov[np.ix_(uq, vr)] += Rqr - xi
+                if r != q:
+                    cov[np.ix_(vr, uq)] += (Rqr - xi).T
+        return cov
+
+
+def predict_cov(p):
+    """Predictive mean and full covariance at the test inputs."""
+    f = Fit(p, keep_test_cols=True).finish()
+    mean, _ = f.predict()
+    return mean, f.predict_cov()
 
 
 def fit_predict(p):

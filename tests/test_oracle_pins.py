@@ -269,3 +269,66 @@ def test_lml_adjoint_matches_finite_differences(B):
     assert abs(val - dense.lml(p)) < 1e-10 * abs(val)
     fd = fd5(p)
     assert np.abs(grad - fd).max() < 1e-6 * max(1.0, np.abs(fd).max())
+
+
+# --- full predictive covariance (Eq. (4) beyond the diagonal) --------------
+
+def test_full_covariance_of_the_full_gp_at_maximal_order():
+    """B = M-1: the dense definition's and the window form's full predictive
+    covariance equal the textbook GP posterior covariance of the noisy
+    outputs, computed by library routines."""
+    p = tiny(7, prior_mean=-0.2)
+    q = p.with_(B=p.M - 1)
+    Sdd = k_same(q.X, q.log_hyp)
+    Sud = k_cross(q.U, q.X, q.log_hyp)
+    ref = k_same(q.U, q.log_hyp) - Sud @ sla.cho_solve(sla.cho_factor(Sdd, lower=True), Sud.T)
+    _, c0 = dense.predict(q, full_cov=True)
+    _, c1 = lma.predict_cov(q)
+    assert rel(c0, ref) < 1e-11 and rel(c1, ref) < 1e-11
+
+
+def test_full_covariance_of_pic_at_order_zero():
+    """B = 0: the full covariance of the PIC prior (exact residual inside each
+    V_m = D_m u U_m, none across blocks), conditioned on D directly."""
+    p = tiny(5).with_(B=0)
+    P = np.vstack([p.X, p.U])
+    Sig = k_same(P, p.log_hyp)
+    Kvs = k_cross(P, p.S, p.log_hyp)
+    Q = Kvs @ np.linalg.solve(k_same(p.S, p.log_hyp), Kvs.T)
+    R = Sig - Q
+    bp, ubp, n = p.block_ptr, p.u_block_ptr, p.n
+    blk = np.empty(P.shape[0], dtype=int)
+    for m in range(p.M):
+        blk[bp[m]:bp[m + 1]] = m
+        blk[n + ubp[m]:n + ubp[m + 1]] = m
+    Spic = Q + R * (blk[:, None] == blk[None, :])
+    D, U = np.arange(n), n + np.arange(p.n_u)
+    F = sla.cho_factor(Spic[np.ix_(D, D)], lower=True)
+    ref = Spic[np.ix_(U, U)] - Spic[np.ix_(U, D)] @ sla.cho_solve(F, Spic[np.ix_(D, U)])
+    _, c0 = dense.predict(p, full_cov=True)
+    _, c1 = lma.predict_cov(p)
+    assert rel(c0, ref) < 1e-11 and rel(c1, ref) < 1e-11
+
+
+@pytest.mark.parametrize("B", [1, 2, 3])
+def test_full_covariance_window_form_equals_the_definition(B):
+    """0 < B < M-1: the window form (banded residual minus the whitened
+    products, plus the low-rank term) equals Eq. (4) of the dense definition
+    entry by entry, on uneven blocks with an empty test block and a support
+    set off the data; its diagonal is the predictive variance; and pairs of
+    test points more than B blocks apart carry only the low-rank term."""
+    p = tiny(11, B=B, s_from_X=False, prior_mean=0.1)
+    _, c0 = dense.predict(p, full_cov=True)
+    f = lma.Fit(p, keep_test_cols=True).finish()
+    c1 = f.predict_cov()
+    scale = np.max(np.abs(c0))
+    assert np.max(np.abs(c1 - c0)) <= 1e-12 * scale
+    _, var = f.predict()
+    assert np.max(np.abs(np.diag(c1) - var)) <= 1e-13 * scale
+    E = f.K_SU.T - f.G
+    low = E @ sla.cho_solve((f.L_dd, True), E.T)
+    ublk = np.repeat(np.arange(p.M), np.diff(p.u_block_ptr))
+    far = np.abs(ublk[:, None] - ublk[None, :]) > B
+    assert far.any()
+    assert np.max(np.abs(c0[far] - low[far])) <= 1e-12 * scale
+    assert np.max(np.abs(c0[~far] - low[~far])) > 1e-6 * scale
