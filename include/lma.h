@@ -112,6 +112,26 @@ lma_status lma_predict(lma_state *f, int64_t n_u, const double *U, const int64_t
                        double *mean, double *var, hipStream_t stream);
 
 /*
+ * Full predictive covariance (Theorem 2's Sigma^LMA_UU, Eq. (4) beyond its
+ * diagonal) at n_u test inputs partitioned as for lma_predict.  cov [n_u][n_u]
+ * (row-major, caller-owned, n_u^2 doubles) receives the covariance of the
+ * noisy test outputs, computed as
+ *   cov_uv = [|q - r| <= B] (R_uv - xi_uv) + E_u^T Sigma_ddot_SS^-1 E_v
+ * for u in test block q and v in test block r: R the residual covariance
+ * (noise on the diagonal), xi_uv the product of the two points' whitened
+ * window rows over the windows that hold both, E_u = K_Su - G_u as for the
+ * variance.  For test blocks more than B apart the residual part of Eq. (1)
+ * cancels exactly, so their entries are the low-rank term alone.  Its
+ * diagonal is lma_predict's variance; it is symmetric up to rounding and, for
+ * 0 < B < M-1, need not be positive semidefinite.  mean [n_u] (or NULL)
+ * receives the predictive mean.  Meant for small test sets: the work and the
+ * output grow as n_u^2.  Synchronises the stream.
+ * Errors: LMA_E_ARG (also n_u > 2^31), LMA_E_HIP, LMA_E_NOMEM.
+ */
+lma_status lma_predict_cov(lma_state *f, int64_t n_u, const double *U, const int64_t *u_block_ptr,
+                           double *mean, double *cov, hipStream_t stream);
+
+/*
  * Log marginal likelihood log N(y; mu, Sigma_bar_DD) of the LMA prior
  * (through the matrix inversion lemma of Eq. (5) and the block factor of
  * Lemma 1), written to *lml (host).  If grad (host, [d+2]) is not NULL it

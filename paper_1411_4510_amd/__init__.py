@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "liblma.so")
 
 LMA_OK, LMA_E_ARG, LMA_E_NOT_PD, LMA_E_HIP, LMA_E_NOMEM, LMA_E_INTERNAL = 0, 1, 2, 3, 4, 5
 PRECISION = {"fp64": 0, "mixed": 1}
-EXPORTS = ("lma_fit", "lma_predict", "lma_lml", "lma_free", "lma_state_lml", "lma_state_bytes", "lma_state_chunks",
+EXPORTS = ("lma_fit", "lma_predict", "lma_predict_cov", "lma_lml", "lma_free", "lma_state_lml", "lma_state_bytes", "lma_state_chunks",
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
            "lma_profile_read", "lma_release_cache")
 PART_EXPORTS = ("lma_kmeans_assign", "lma_kmeans_update", "lma_kmeans", "lma_chain_order")
@@ -85,6 +85,8 @@ def load(path: str = LIB_PATH):
     lib.lma_fit.restype = st
     lib.lma_predict.argtypes = [vp, i64, vp, ctypes.POINTER(i64), vp, vp, vp]
     lib.lma_predict.restype = st
+    lib.lma_predict_cov.argtypes = [vp, i64, vp, ctypes.POINTER(i64), vp, vp, vp]
+    lib.lma_predict_cov.restype = st
     lib.lma_lml.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_double),
                             ctypes.POINTER(ctypes.c_double), vp]
     lib.lma_lml.restype = st
@@ -203,6 +205,21 @@ class State:
                                 ctypes.c_void_p(var.data_ptr()) if var is not None else None,
                                 _stream(torch, stream)))
         return mean, var
+
+    def predict_cov(self, U, u_block_ptr, want_mean=True, stream=None):
+        """Predictive mean (or None) and full covariance [n_u, n_u] (device
+        float64 tensors)."""
+        import torch
+        Ud = _dev(U, torch)
+        ubp = np.ascontiguousarray(np.asarray(u_block_ptr, dtype=np.int64))
+        n_u = Ud.shape[0]
+        mean = torch.empty(n_u, dtype=torch.float64, device="cuda") if want_mean else None
+        cov = torch.empty((n_u, n_u), dtype=torch.float64, device="cuda")
+        _check(_lib.lma_predict_cov(self._h, n_u, ctypes.c_void_p(Ud.data_ptr()),
+                                    ubp.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    ctypes.c_void_p(mean.data_ptr()) if mean is not None else None,
+                                    ctypes.c_void_p(cov.data_ptr()), _stream(torch, stream)))
+        return mean, cov
 
     def lml(self):
         out = ctypes.c_double()

@@ -1140,11 +1140,16 @@ void predict_windows(lma_state& f, Run<TW>& run, int64_t n_u, const std::vector<
 
 template <typename TW>
 static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64_t* u_block_ptr, double* mean,
-                         double* var, hipStream_t st) {
+                         double* var, hipStream_t st, double* cov = nullptr) {
   const int64_t d = f.d, sp = f.sp, M = f.M;
   const int Ts = (int)f.Ts;
   const bool mixed = f.mixed();
   std::vector<int64_t> ubp(u_block_ptr, u_block_ptr + M + 1);
+  // The full covariance needs everything the variance needs (whitened test
+  // rows of every window, L_ddot^-1 E_u); without caller buffers for the mean
+  // or the variance they live in the workspace.
+  const bool want_cov = cov != nullptr;
+  const bool need_var = var != nullptr || want_cov;
   // With the window factors held one chunk at a time (memory budget), each
   // chunk is factored again with the test rows appended, and the test rows'
   // solutions are kept for one chunk at a time.
@@ -1154,7 +1159,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   // of blocks q-B .. q+B (all windows that hold u lie there), formed once and
   // read by the B+1 window solves of u (not in the memory-budget mode).
   const int64_t wsz = (int64_t)sizeof(TW);
-  const bool use_tband = var != nullptr && n_u > 0 && !stream && std::getenv("LMA_NO_BAND") == nullptr;
+  const bool use_tband = need_var && n_u > 0 && !stream && std::getenv("LMA_NO_BAND") == nullptr;
   std::vector<BandItem> tb_items;
   std::vector<int64_t> tb_row;
   int64_t tb_elems = 0;
@@ -1193,7 +1198,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
       const int64_t qhi = std::min(m + f.B, M - 1);
       const int64_t nr = ubp[qhi + 1] - ubp[m];
       Xoff[m] = acc;
-      if (var) acc += nr * (int64_t)f.Tm[m] * TB;
+      if (need_var) acc += nr * (int64_t)f.Tm[m] * TB;
     }
     xel = std::max(xel, acc);
   }
@@ -1214,6 +1219,35 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   const int64_t o_twm = ar.reserve(4 * M);
   const int64_t o_stat = ar.reserve(4 * (M + 2));
   const int64_t o_ld = ar.reserve(8 * (M + 2) * (int64_t)maxT);  // log-diagonals of refactored windows
+  const int64_t o_mtmp = mean ? 0 : ar.reserve(8 * n_u);
+  const int64_t o_vtmp = (want_cov && !var) ? ar.reserve(8 * n_u) : 0;
+  double* mean_p = mean;
+  double* var_p = var;
+  // full covariance: residual entries of the test pairs inside the band
+  // (k_band with the test points as rows and columns), the low-rank term
+  // (L_ddot^-1 E)^T (L_ddot^-1 E) over every tile pair, and the whitened
+  // products xi of the windows that hold both points of a pair
+  std::vector<BandItem> cb_items;
+  std::vector<GemmTerm<double>> cterms;
+  std::vector<GemmOut> couts;
+  std::vector<GemmTerm<TW>> xterms;
+  std::vector<GemmOut> xouts;
+  std::vector<int> xsplit;   // xi outputs of chunk ci: [xsplit[ci], xsplit[ci+1])
+  if (want_cov) {
+    for (int64_t q = 0; q < M; ++q)
+      for (int64_t r = std::max<int64_t>(0, q - f.B); r <= std::min<int64_t>(M - 1, q + f.B); ++r)
+        for (int64_t u0 = ubp[q]; u0 < ubp[q + 1]; u0 += TB)
+          for (int64_t v0 = ubp[r]; v0 < ubp[r + 1]; v0 += TB) {
+            BandItem it;
+            it.p0 = u0;
+            it.q0 = v0;
+            it.off = u0 * n_u + v0;
+            it.ld = n_u;
+            it.nr = (int)std::min<int64_t>(TB, ubp[q + 1] - u0);
+            it.nc = (int)std::min<int64_t>(TB, ubp[r + 1] - v0);
+            cb_items.push_back(it);
+          }
+  }
   // runs
   Run<double> runS;
   std::vector<Run<TW>> runsW(nch);
@@ -1236,6 +1270,13 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     outs.clear();
     kvcols.clear();
     kvitems.clear();
+    cterms.clear();
+    couts.clear();
+    xterms.clear();
+    xouts.clear();
+    xsplit.clear();
+    if (!mean) mean_p = at<double>(ar, o_mtmp);
+    if (want_cov && !var) var_p = at<double>(ar, o_vtmp);
     // S run in solve-only mode: right-hand sides are the test rows -> V_U^T
     const int Rn = (int)cdiv(n_u, TB);
     runS.add_problem(Ts, Rn, 0, true, -1);
@@ -1266,7 +1307,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
           KvItem it = kv_item(at<double>(ar, o_Us64) + u0 * d, (int)std::min<int64_t>(TB, ubp[q + 1] - u0), c0, c1);
           it.vt = at<double>(ar, o_VtU64) + u0 * sp;
           it.h0 = at<double>(ar, o_hq) + q * sp;
-          it.out0 = mean + u0;
+          it.out0 = mean_p + u0;
           kvitems.push_back(it);
         }
       }
@@ -1278,7 +1319,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     const double* Vt = f.ptr<double>(f.o_Vt64);
     const TW* c = mixed ? (const TW*)f.ptr<float>(f.o_c32) : (const TW*)f.ptr<double>(f.o_c64);
     TW* winbase = reinterpret_cast<TW*>(f.ptr<char>(f.o_win));
-    if (!var) return;
+    if (!var_p) return;
     for (int ci = 0; ci < nch; ++ci) {
       predict_windows<TW>(f, runsW[ci], n_u, ubp, Us, VtU, at<TW>(ar, o_X), Xoff, winbase, Xs, Vt, c, pchunk[ci],
                           pchunk[ci + 1], stream, use_tband);
@@ -1347,6 +1388,63 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
       runD.rt.push_back(t);
     }
     runD.schedule();
+    if (!want_cov) return;
+    // low-rank term over every tile pair: rows of L_ddot^-1 E (the Sigma_ddot
+    // run's right-hand sides, in place in G)
+    for (int64_t u0 = 0; u0 < n_u; u0 += TB)
+      for (int64_t v0 = 0; v0 < n_u; v0 += TB) {
+        const int rows = (int)std::min<int64_t>(TB, n_u - u0), cols = (int)std::min<int64_t>(TB, n_u - v0);
+        GemmOut o = gemm_out(cov + u0 * n_u + v0, n_u, rows, cols, 1, (int)cterms.size());
+        GemmTerm<double> tm;
+        tm.a = at<double>(ar, o_G) + u0 * ldG;
+        tm.lda = ldG;
+        tm.anr = rows;
+        tm.b = at<double>(ar, o_G) + v0 * ldG;
+        tm.ldb = ldG;
+        tm.bnr = cols;
+        tm.k0 = 0;
+        tm.k1 = (int32_t)sp;
+        cterms.push_back(tm);
+        o.t1 = (int32_t)cterms.size();
+        couts.push_back(o);
+      }
+    // xi of the pair tiles (u in block q, v in block r, |q - r| <= B; a = min,
+    // b = max): D rows of windows max(0, b-B) .. a-1, all rows of window a;
+    // subtracted.  One output per tile pair and chunk of windows.
+    xsplit.assign(1, 0);
+    for (int ci = 0; ci < nch; ++ci) {
+      for (int64_t q = 0; q < M; ++q)
+        for (int64_t r = std::max<int64_t>(0, q - f.B); r <= std::min<int64_t>(M - 1, q + f.B); ++r) {
+          const int64_t a = std::min(q, r), b = std::max(q, r);
+          const int64_t m0 = std::max<int64_t>({(int64_t)0, b - f.B, pchunk[ci]});
+          const int64_t m1 = std::min<int64_t>(a + 1, pchunk[ci + 1]);
+          if (m0 >= m1) continue;
+          for (int64_t u0 = ubp[q]; u0 < ubp[q + 1]; u0 += TB)
+            for (int64_t v0 = ubp[r]; v0 < ubp[r + 1]; v0 += TB) {
+              const int rows = (int)std::min<int64_t>(TB, ubp[q + 1] - u0);
+              const int cols = (int)std::min<int64_t>(TB, ubp[r + 1] - v0);
+              GemmOut o = gemm_out(cov + u0 * n_u + v0, n_u, rows, cols, 1, (int)xterms.size());
+              for (int64_t m = m0; m < m1; ++m) {
+                const WinGeom g = win_geom(f.bp, M, f.B, m);
+                const int64_t ldx = (int64_t)g.T * TB;
+                const TW* Xm = at<TW>(ar, o_X) + Xoff[m];
+                GemmTerm<TW> tm;
+                tm.a = Xm + (u0 - ubp[m]) * ldx;
+                tm.lda = ldx;
+                tm.anr = rows;
+                tm.b = Xm + (v0 - ubp[m]) * ldx;
+                tm.ldb = ldx;
+                tm.bnr = cols;
+                tm.k0 = m == a ? 0 : g.tw * TB;
+                tm.k1 = g.T * TB;
+                xterms.push_back(tm);
+              }
+              o.tneg = o.t1 = (int32_t)xterms.size();
+              xouts.push_back(o);
+            }
+        }
+      xsplit.push_back((int)xouts.size());
+    }
   };
   build(nullptr);
   // dG outputs: one launch per delta; record split points
@@ -1370,6 +1468,11 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   const int64_t o_kvi = ar.reserve(sizeof(KvItem) * std::max<size_t>(kvitems.size(), 1));
   const int64_t o_terms = ar.reserve(sizeof(GemmTerm<TW>) * std::max<size_t>(terms.size(), 1));
   const int64_t o_outs = ar.reserve(sizeof(GemmOut) * std::max<size_t>(outs.size(), 1));
+  const int64_t o_cbi = ar.reserve(sizeof(BandItem) * std::max<size_t>(cb_items.size(), 1));
+  const int64_t o_cterms = ar.reserve(sizeof(GemmTerm<double>) * std::max<size_t>(cterms.size(), 1));
+  const int64_t o_couts = ar.reserve(sizeof(GemmOut) * std::max<size_t>(couts.size(), 1));
+  const int64_t o_xterms = ar.reserve(sizeof(GemmTerm<TW>) * std::max<size_t>(xterms.size(), 1));
+  const int64_t o_xouts = ar.reserve(sizeof(GemmOut) * std::max<size_t>(xouts.size(), 1));
   ar.cap = ar.used;
   void* mem = devcache::get((size_t)ar.cap);
   if (!mem) throw Err{LMA_E_NOMEM, "device allocation of the prediction workspace failed"};
@@ -1406,6 +1509,21 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     if (!kvitems.empty())
       HIPCHK(hipMemcpyAsync(at<char>(ar, o_kvi), kvitems.data(), sizeof(KvItem) * kvitems.size(),
                             hipMemcpyHostToDevice, st));
+    if (!cb_items.empty())
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_cbi), cb_items.data(), sizeof(BandItem) * cb_items.size(),
+                            hipMemcpyHostToDevice, st));
+    if (!cterms.empty()) {
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_cterms), cterms.data(), sizeof(GemmTerm<double>) * cterms.size(),
+                            hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_couts), couts.data(), sizeof(GemmOut) * couts.size(),
+                            hipMemcpyHostToDevice, st));
+    }
+    if (!xterms.empty()) {
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_xterms), xterms.data(), sizeof(GemmTerm<TW>) * xterms.size(),
+                            hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(at<char>(ar, o_xouts), xouts.data(), sizeof(GemmOut) * xouts.size(),
+                            hipMemcpyHostToDevice, st));
+    }
   }
   std::vector<int32_t> ublk(n_u);
   for (int64_t q = 0; q < M; ++q)
@@ -1481,7 +1599,40 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     prof::timed(prof::OTHER, 0.0, st, [&] { launch_kvec(kv, st); });
     HIPCHK(hipGetLastError());
   }
-  if (!var) {
+  if (want_cov) {
+    // covariance: zero, then the residual entries of the in-band pairs
+    prof::timed(prof::OTHER, 0.0, st, [&] { launch_zero(cov, n_u * n_u, st); });
+    HIPCHK(hipGetLastError());
+    BandArgs<double> cb{};
+    cb.items = at<BandItem>(ar, o_cbi);
+    cb.nitems = (int32_t)cb_items.size();
+    cb.d = (int)d;
+    cb.vlen = (int)sp;
+    cb.noise = 1;  // one point set: sn2 on the diagonal
+    cb.vld = sp;
+    cb.Vt = at<double>(ar, o_VtU64);
+    cb.Xs = at<double>(ar, o_Us64);
+    cb.Vr = at<double>(ar, o_VtU64);
+    cb.Xr = at<double>(ar, o_Us64);
+    cb.sf2 = f.sf2;
+    cb.sn2 = f.sn2;
+    cb.band = cov;
+    double fl = 0.0;
+    if (prof::on)
+      for (const BandItem& it : cb_items) fl += 2.0 * it.nr * it.nc * (double)f.s;
+    prof::timed(prof::GEMM, fl, st, [&] { launch_band<double>(cb, st); });
+    HIPCHK(hipGetLastError());
+  }
+  auto x_launch = [&](int ci) {
+    if (!want_cov) return;
+    const int a0 = xsplit[ci], a1 = xsplit[ci + 1];
+    if (a1 > a0)
+      prof::timed(prof::GEMM, prof::on ? gemm_flops(xterms, xouts, a0, a1) : 0.0, st, [&] {
+        launch_tile_gemm<TW>(at<GemmTerm<TW>>(ar, o_xterms), at<GemmOut>(ar, o_xouts) + a0, a1 - a0, st);
+      });
+    HIPCHK(hipGetLastError());
+  };
+  if (!var_p) {
     HIPCHK(hipStreamSynchronize(st));
     prof::flush();
     return;
@@ -1534,6 +1685,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
     exec(runsW[0], invs, (int)sp, false, use_tband);
     for (int dl = 0; dl <= f.B; ++dl) g_launch(dl_split[dl], dl_split[dl + 1]);
     xi_launch(0, M, false);
+    x_launch(0);
   } else {
     HIPCHK(hipMemsetAsync(at<double>(ar, o_G), 0, 8 * n_u * ldG, st));
     for (int ci = 0; ci < nch; ++ci) {
@@ -1543,6 +1695,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
         g_launch(gsplit[k], gsplit[k + 1]);
       }
       xi_launch(pchunk[ci], pchunk[ci + 1], ci > 0);
+      x_launch(ci);
     }
   }
   PredArgs pa;
@@ -1560,7 +1713,7 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   pa.sf2 = f.sf2;
   pa.sn2 = f.sn2;
   pa.mean = nullptr;
-  pa.var = var;
+  pa.var = var_p;
   pa.vn = at<double>(ar, o_vn);
   pa.xi = at<double>(ar, o_xi);
   prof::timed(prof::OTHER, 0.0, st, [&] { launch_pred_E(pa, st); });
@@ -1568,6 +1721,12 @@ static void predict_impl(lma_state& f, int64_t n_u, const double* U, const int64
   exec(runD, f.ptr<double>(f.o_Ldd_inv), 0);
   prof::timed(prof::OTHER, 0.0, st, [&] { launch_pred_var(pa, st); });
   HIPCHK(hipGetLastError());
+  if (want_cov && !couts.empty()) {
+    prof::timed(prof::GEMM, prof::on ? gemm_flops(cterms, couts, 0, (int64_t)couts.size()) : 0.0, st, [&] {
+      launch_tile_gemm<double>(at<GemmTerm<double>>(ar, o_cterms), at<GemmOut>(ar, o_couts), (int)couts.size(), st);
+    });
+    HIPCHK(hipGetLastError());
+  }
   HIPCHK(hipStreamSynchronize(st));
   prof::flush();
 }
@@ -1616,6 +1775,37 @@ lma_status lma_predict(lma_state* f, int64_t n_u, const double* U, const int64_t
       predict_impl<float>(*f, n_u, U, u_block_ptr, mean, var, stream);
     else
       predict_impl<double>(*f, n_u, U, u_block_ptr, mean, var, stream);
+    return LMA_OK;
+  } catch (const Err& e) {
+    set_err(e);
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return LMA_E_NOMEM;
+  } catch (const std::exception& e) {
+    g_err = std::string("internal error: ") + e.what();
+    return LMA_E_INTERNAL;
+  }
+}
+
+lma_status lma_predict_cov(lma_state* f, int64_t n_u, const double* U, const int64_t* u_block_ptr, double* mean,
+                           double* cov, hipStream_t stream) {
+  g_err.clear();
+  g_failed = -3;
+  try {
+    if (!f) throw Err{LMA_E_ARG, "state is NULL"};
+    if (n_u < 0) throw Err{LMA_E_ARG, "n_u < 0"};
+    if (n_u == 0) return LMA_OK;
+    if (n_u > ((int64_t)1 << 31)) throw Err{LMA_E_ARG, "n_u too large for a full covariance"};
+    if (!U || !u_block_ptr || !cov) throw Err{LMA_E_ARG, "NULL array"};
+    if (u_block_ptr[0] != 0 || u_block_ptr[f->M] != n_u)
+      throw Err{LMA_E_ARG, "u_block_ptr must start at 0 and end at n_u"};
+    for (int64_t m = 0; m < f->M; ++m)
+      if (u_block_ptr[m + 1] < u_block_ptr[m]) throw Err{LMA_E_ARG, "u_block_ptr must be non-decreasing"};
+    if (f->mixed())
+      predict_impl<float>(*f, n_u, U, u_block_ptr, mean, nullptr, stream, cov);
+    else
+      predict_impl<double>(*f, n_u, U, u_block_ptr, mean, nullptr, stream, cov);
     return LMA_OK;
   } catch (const Err& e) {
     set_err(e);
