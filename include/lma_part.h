@@ -59,6 +59,21 @@ lma_status lma_kmeans_update(const double *P, int64_t n, int32_t d, const int32_
                              int64_t *count, hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the centre
+ * update of lma_kmeans_update with the same arguments and the same result bit
+ * for bit, but its partial sums live in a fixed 16 MiB scratch array that the
+ * library holds on each GPU until the process ends, and it never allocates,
+ * frees or synchronises (work is only enqueued on the stream).  Needs
+ * 24*k*d + 8*k <= 16 MiB (k*d up to about 690000); larger sizes are rejected
+ * with LMA_E_ARG.  Every call on one GPU shares that GPU's scratch: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  Errors: LMA_E_ARG, LMA_E_HIP.
+ */
+lma_status lma_kmeans_update_noalloc(const double *P, int64_t n, int32_t d, const int32_t *label, int32_t k,
+                                     double *C, int64_t *count, hipStream_t stream);
+
+/*
  * Lloyd's iteration: iters rounds of (assign, update) starting from the
  * centres in C (in/out), then a final assignment into label [n] (and dist2
  * [n] or NULL) against the final centres.  iters >= 0.  Synchronises the

@@ -24,7 +24,8 @@ PRECISION = {"fp64": 0, "mixed": 1}
 EXPORTS = ("lma_fit", "lma_predict", "lma_predict_cov", "lma_lml", "lma_free", "lma_state_lml", "lma_state_bytes", "lma_state_chunks",
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
            "lma_profile_read", "lma_release_cache")
-PART_EXPORTS = ("lma_kmeans_assign", "lma_kmeans_update", "lma_kmeans", "lma_chain_order")
+PART_EXPORTS = ("lma_kmeans_assign", "lma_kmeans_update", "lma_kmeans_update_noalloc", "lma_kmeans",
+                "lma_chain_order")
 DS_EXPORTS = ("lma_ds_create", "lma_ds_free", "lma_ds_set_params", "lma_ds_get_params", "lma_ds_features",
               "lma_ds_forward", "lma_ds_backward", "lma_ds_adam")
 
@@ -128,6 +129,8 @@ def load(path: str = LIB_PATH):
     lib.lma_kmeans_assign.restype = st
     lib.lma_kmeans_update.argtypes = [vp, i64, i32, vp, i32, vp, vp, vp]
     lib.lma_kmeans_update.restype = st
+    lib.lma_kmeans_update_noalloc.argtypes = [vp, i64, i32, vp, i32, vp, vp, vp]
+    lib.lma_kmeans_update_noalloc.restype = st
     lib.lma_kmeans.argtypes = [vp, i64, i32, vp, i32, i32, vp, vp, vp]
     lib.lma_kmeans.restype = st
     lib.lma_chain_order.argtypes = [vp, i32, i32, vp]

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include "lma_part.h"
@@ -35,6 +36,13 @@ constexpr int NTU = 64;    // threads per workgroup, update
 constexpr int MAX_K = 65536;
 constexpr int64_t CHUNK = 4096;         // points per partial sum of the update
 constexpr int64_t PART_BYTES = 1ll << 30;  // partial sums held at once
+
+// Scratch of the allocation-free centre update (lma_kmeans_update_noalloc):
+// one copy per GPU, held until the process ends.  Host code never passes the
+// symbol itself to a kernel (on the host it is only a stand-in); it uses the
+// device address that hipGetSymbolAddress returns for the current device.
+constexpr int64_t NOALLOC_BYTES = 16ll << 20;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
 
 __global__ __launch_bounds__(NTA) void k_km_assign(const double* __restrict__ P, int64_t n, int d,
                                                    const double* __restrict__ C, int k, int32_t* __restrict__ label,
@@ -155,24 +163,17 @@ void assign(const double* P, int64_t n, int32_t d, const double* C, int32_t k, i
   HIPCHK(hipGetLastError());
 }
 
-// Centre update in chunk order.  Chunks are processed in groups whose partial
-// sums fit PART_BYTES; running sums carry the order across groups.  The
-// scratch block comes from the library's device cache and goes back after a
-// stream synchronisation.
-void update(const double* P, int64_t n, int32_t d, const int32_t* label, int32_t k, double* C, int64_t* count,
-            hipStream_t st) {
+// Centre update in chunk order.  Chunks are processed in groups of `group`
+// chunks whose partial sums sit at the start of the workspace `mem`; running
+// sums (after them) carry the order across groups, so the result does not
+// depend on the group size.  Returns the launch status; enqueues only.
+hipError_t update_launch(const double* P, int64_t n, int32_t d, const int32_t* label, int32_t k, double* C,
+                         int64_t* count, int64_t group, char* mem, hipStream_t st) {
   using namespace lma::part;
   const int64_t kd = (int64_t)k * d;
   const int64_t nch = n > 0 ? (n + CHUNK - 1) / CHUNK : 0;
   const int64_t per = (int64_t)sizeof(double) * kd + (int64_t)sizeof(int64_t) * k;
-  int64_t cap = PART_BYTES;
-  if (const char* env = std::getenv("LMA_KMEANS_PART_BYTES")) cap = std::max<long long>(1, std::atoll(env));
-  const int64_t group = nch == 0 ? 0 : std::max<int64_t>(1, std::min<int64_t>(nch, cap / per));
   const int64_t nbx = (kd + NTU - 1) / NTU;
-  if (group * nbx > 0x7fffffff) throw Err{LMA_E_ARG, "too many centres x coordinates for one launch"};
-  const size_t bytes = (size_t)(group * per + kd * (int64_t)(sizeof(double) + sizeof(int64_t)));
-  char* mem = static_cast<char*>(lmart::devcache::get(bytes));
-  if (!mem) throw Err{LMA_E_NOMEM, "device allocation for the centre update failed"};
   double* part = reinterpret_cast<double*>(mem);
   int64_t* pcnt = reinterpret_cast<int64_t*>(mem + sizeof(double) * group * kd);
   double* srun = reinterpret_cast<double*>(mem + group * per);
@@ -193,10 +194,77 @@ void update(const double* P, int64_t n, int32_t d, const int32_t* label, int32_t
                        crun, ch0 == 0 ? 1 : 0, ch0 + ng >= nch ? 1 : 0, C, count);
     err = hipGetLastError();
   }
+  return err;
+}
+
+// Bytes of partial sums per chunk, and of the running sums.
+int64_t update_per_chunk(int32_t d, int32_t k) {
+  return (int64_t)sizeof(double) * k * d + (int64_t)sizeof(int64_t) * k;
+}
+int64_t update_running(int32_t d, int32_t k) {
+  return (int64_t)(sizeof(double) + sizeof(int64_t)) * k * d;
+}
+
+void check_launch_size(int64_t group, int32_t d, int32_t k) {
+  const int64_t nbx = ((int64_t)k * d + lma::part::NTU - 1) / lma::part::NTU;
+  if (group * nbx > 0x7fffffff) throw Err{LMA_E_ARG, "too many centres x coordinates for one launch"};
+}
+
+// The update with a workspace from the library's device cache (partial sums
+// of at most PART_BYTES at once), returned after a stream synchronisation.
+void update(const double* P, int64_t n, int32_t d, const int32_t* label, int32_t k, double* C, int64_t* count,
+            hipStream_t st) {
+  using namespace lma::part;
+  const int64_t nch = n > 0 ? (n + CHUNK - 1) / CHUNK : 0;
+  const int64_t per = update_per_chunk(d, k);
+  int64_t cap = PART_BYTES;
+  if (const char* env = std::getenv("LMA_KMEANS_PART_BYTES")) cap = std::max<long long>(1, std::atoll(env));
+  const int64_t group = nch == 0 ? 0 : std::max<int64_t>(1, std::min<int64_t>(nch, cap / per));
+  check_launch_size(group, d, k);
+  const size_t bytes = (size_t)(group * per + update_running(d, k));
+  char* mem = static_cast<char*>(lmart::devcache::get(bytes));
+  if (!mem) throw Err{LMA_E_NOMEM, "device allocation for the centre update failed"};
+  const hipError_t err = update_launch(P, n, d, label, k, C, count, group, mem, st);
   const hipError_t es = hipStreamSynchronize(st);
   lmart::devcache::put(mem, bytes);
   if (err != hipSuccess) throw Err{LMA_E_HIP, std::string("k-means update launch: ") + hipGetErrorString(err)};
   if (es != hipSuccess) throw Err{LMA_E_HIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(es)};
+}
+
+// Device address of the scratch array on the current device, looked up once
+// per device (each GPU holds its own copy at its own address).
+char* scratch_ptr() {
+  static std::mutex mu;
+  static std::vector<char*> ptrs;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)ptrs.size() <= dev) ptrs.resize(dev + 1, nullptr);
+  if (!ptrs[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(lma::part::scratch));
+    if (e != hipSuccess || !ptr)
+      throw Err{LMA_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e)};
+    ptrs[dev] = static_cast<char*>(ptr);
+  }
+  return ptrs[dev];
+}
+
+// The update in the fixed scratch array: no allocation and no synchronisation.
+void update_noalloc(const double* P, int64_t n, int32_t d, const int32_t* label, int32_t k, double* C,
+                    int64_t* count, hipStream_t st) {
+  using namespace lma::part;
+  const int64_t nch = n > 0 ? (n + CHUNK - 1) / CHUNK : 0;
+  const int64_t per = update_per_chunk(d, k);
+  const int64_t room = NOALLOC_BYTES - update_running(d, k);
+  if (room < per)
+    throw Err{LMA_E_ARG, "k * d too large for the allocation-free update: need 24 k d + 8 k <= " +
+                             std::to_string(NOALLOC_BYTES) + " bytes"};
+  const int64_t group = nch == 0 ? 0 : std::max<int64_t>(1, std::min<int64_t>(nch, room / per));
+  check_launch_size(group, d, k);
+  char* mem = scratch_ptr();
+  const hipError_t err = update_launch(P, n, d, label, k, C, count, group, mem, st);
+  if (err != hipSuccess) throw Err{LMA_E_HIP, std::string("k-means update launch: ") + hipGetErrorString(err)};
 }
 
 template <class F>
@@ -281,6 +349,15 @@ lma_status lma_kmeans_update(const double* P, int64_t n, int32_t d, const int32_
     check_shape(P, n, d, k);
     if (!C || (n > 0 && !label)) throw Err{LMA_E_ARG, "NULL array"};
     update(P, n, d, label, k, C, count, stream);
+  });
+}
+
+lma_status lma_kmeans_update_noalloc(const double* P, int64_t n, int32_t d, const int32_t* label, int32_t k,
+                                     double* C, int64_t* count, hipStream_t stream) {
+  return guard([&] {
+    check_shape(P, n, d, k);
+    if (!C || (n > 0 && !label)) throw Err{LMA_E_ARG, "NULL array"};
+    update_noalloc(P, n, d, label, k, C, count, stream);
   });
 }
 
