@@ -2,14 +2,16 @@
  * lma_part.h -- C ABI of the clustering steps that partition the data into
  * blocks (gfx950).
  *
- * LMA needs the training and test inputs partitioned into M blocks (section
- * "Low-Rank-cum-Markov Approximation"; the paper leaves the scheme to a
- * clustering method of earlier work).  The library takes the partition as an
- * input (block_ptr in lma.h); these entry points run the data-parallel part
- * of a k-means partitioner on the GPU: the nearest-centre assignment of every
- * point and the centre update of Lloyd's iteration.  Seeding, a bound on the
- * block sizes and the order of the blocks along the Markov chain are left to
- * the caller.
+ * LMA needs the training and test inputs partitioned into M blocks, ordered
+ * so that the B blocks after each one are its most correlated neighbours
+ * (section "Low-Rank-cum-Markov Approximation"; the paper leaves the scheme
+ * to a simple parallelised clustering method of earlier work).  The library
+ * takes the partition as an input (block_ptr in lma.h); these entry points
+ * compute one on the GPU: k-means++ seeding, Lloyd's iteration (nearest-centre
+ * assignment and centre update), a capacity-bounded assignment that keeps
+ * every block between lo and hi points, the order of the blocks along the
+ * Markov chain, and lma_partition, which composes them into block-contiguous
+ * permutations of the training and test points.
  *
  * Arithmetic (fixed, so that results are reproducible bit for bit):
  *   - squared distance of point p to centre c: the sum over t = 0..d-1, in that
@@ -82,6 +84,70 @@ lma_status lma_kmeans_update_noalloc(const double *P, int64_t n, int32_t d, cons
  */
 lma_status lma_kmeans(const double *P, int64_t n, int32_t d, double *C, int32_t k, int32_t iters, int32_t *label,
                       double *dist2, hipStream_t stream);
+
+/*
+ * k-means++ seeding (D^2 sampling) of k centres among the n points P [n][d].
+ * The first centre is point floor(rand[0] * n / 2^32); centre j >= 1 is drawn
+ * with probability proportional to each point's squared distance to its
+ * nearest centre so far, using integer weights: with e the binary exponent of
+ * the largest such distance (max = f 2^e, 1/2 <= f < 1) and
+ * W = 63 - bitlength(n), weight_i = floor(dist_i * 2^(W - e)); with T their sum,
+ * the centre is the first point whose running weight sum exceeds
+ * floor(rand[j] * T / 2^32) (if T = 0, point floor(rand[j] * n / 2^32)).
+ * Integer sums make the draw independent of the summation order.
+ * rand (host) [k]: the caller's random 32-bit integers.  C [k][d] receives
+ * the centres (copies of the drawn points), index [k] (device, or NULL) their
+ * point indices.  Points must be finite.  1 <= k <= 65536, n >= 1.
+ * Synchronises the stream.  Errors: LMA_E_ARG, LMA_E_HIP, LMA_E_NOMEM.
+ */
+lma_status lma_kmeans_seed(const double *P, int64_t n, int32_t d, int32_t k, const uint32_t *rand, double *C,
+                           int64_t *index, hipStream_t stream);
+
+/*
+ * Capacity-bounded assignment: label [n] receives a centre for every point
+ * such that every centre holds between lo and hi points (requires
+ * 0 <= lo <= hi, hi >= 1, k*lo <= n <= k*hi).
+ *   Upper bound, in rounds: every point without a centre proposes to its
+ *   nearest centre among those holding fewer than hi points; a centre with
+ *   room for r more points accepts all its proposers if they are at most r,
+ *   else its r nearest (smallest squared distance, ties to the lower point
+ *   index).  At most k + 1 rounds.
+ *   Lower bound, for each centre c holding fewer than lo points, in
+ *   increasing c: the point nearest to c (ties to the lower index) among the
+ *   points of centres that hold more than lo moves to c, until c holds lo.
+ * Distances and nearest centres as in lma_kmeans_assign; every decision is
+ * exact, so the labels equal a sequential evaluation of these rules bit for
+ * bit.  count [k] (device, or NULL) receives the block sizes, *rounds (host,
+ * or NULL) the number of proposal rounds.  Points and centres must be finite.
+ * Synchronises the stream once per round.
+ * Errors: LMA_E_ARG, LMA_E_HIP, LMA_E_NOMEM.
+ */
+lma_status lma_bounded_assign(const double *P, int64_t n, int32_t d, const double *C, int32_t k, int64_t lo,
+                              int64_t hi, int32_t *label, int64_t *count, int32_t *rounds, hipStream_t stream);
+
+/*
+ * The block partition of training inputs X [n][d] and test inputs U [n_u][d]
+ * into M blocks (section "Low-Rank-cum-Markov Approximation"):
+ *   1. k-means++ seeding of M centres (lma_kmeans_seed with rand (host) [M]);
+ *   2. iters rounds of Lloyd's iteration (lma_kmeans);
+ *   3. capacity-bounded assignment of X with block sizes in [lo, hi]
+ *      (lma_bounded_assign);
+ *   4. block centres = the mean of each block's points (lma_kmeans_update);
+ *   5. block order = the chain of lma_chain_order through the block centres:
+ *      block m is the chain's m-th centre;
+ *   6. every test point goes to the block of its nearest block centre;
+ *   7. perm [n] (device) lists the training points block by block, the points
+ *      of a block in increasing index (X[perm] is block-contiguous);
+ *      block_ptr (host) [M+1] the block boundaries; u_perm [n_u] (device) and
+ *      u_block_ptr (host) [M+1] the same for the test points (NULL when
+ *      n_u = 0; empty test blocks are possible).
+ * centres [M][d] (device, or NULL) receives the block centres in block order.
+ * Points must be finite.  Synchronises the stream.
+ * Errors: LMA_E_ARG, LMA_E_HIP, LMA_E_NOMEM.
+ */
+lma_status lma_partition(const double *X, int64_t n, const double *U, int64_t n_u, int32_t d, int32_t M, int64_t lo,
+                         int64_t hi, int32_t iters, const uint32_t *rand, int64_t *perm, int64_t *block_ptr,
+                         int64_t *u_perm, int64_t *u_block_ptr, double *centres, hipStream_t stream);
 
 /*
  * Order of the blocks along the Markov chain (host function, no device work):

@@ -25,7 +25,7 @@ EXPORTS = ("lma_fit", "lma_predict", "lma_predict_cov", "lma_lml", "lma_free", "
            "lma_last_error", "lma_failed_block", "lma_version", "lma_profile_enable",
            "lma_profile_read", "lma_release_cache")
 PART_EXPORTS = ("lma_kmeans_assign", "lma_kmeans_update", "lma_kmeans_update_noalloc", "lma_kmeans",
-                "lma_chain_order")
+                "lma_chain_order", "lma_kmeans_seed", "lma_bounded_assign", "lma_partition")
 DS_EXPORTS = ("lma_ds_create", "lma_ds_free", "lma_ds_set_params", "lma_ds_get_params", "lma_ds_features",
               "lma_ds_forward", "lma_ds_backward", "lma_ds_adam")
 
@@ -135,6 +135,12 @@ def load(path: str = LIB_PATH):
     lib.lma_kmeans.restype = st
     lib.lma_chain_order.argtypes = [vp, i32, i32, vp]
     lib.lma_chain_order.restype = st
+    lib.lma_kmeans_seed.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp]
+    lib.lma_kmeans_seed.restype = st
+    lib.lma_bounded_assign.argtypes = [vp, i64, i32, vp, i32, i64, i64, vp, vp, vp, vp]
+    lib.lma_bounded_assign.restype = st
+    lib.lma_partition.argtypes = [vp, i64, vp, i64, i32, i32, i64, i64, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.lma_partition.restype = st
     _lib = lib
     return lib
 
@@ -418,3 +424,58 @@ def chain_order(C):
 def version():
     load()
     return _lib.lma_version().decode()
+
+
+def kmeans_seed(P, k, rand, stream=None):
+    """k-means++ seeding: (centres [k, d], point indices int64 [k]) as device
+    tensors; rand: k random 32-bit integers (host)."""
+    import torch
+    load()
+    Pd = _dev(P, torch)
+    r = np.ascontiguousarray(np.asarray(rand, dtype=np.uint32))
+    if r.shape != (k,):
+        raise ValueError("rand must hold k values")
+    C = torch.empty((k, Pd.shape[1]), dtype=torch.float64, device="cuda")
+    idx = torch.empty(k, dtype=torch.int64, device="cuda")
+    _check(_lib.lma_kmeans_seed(_ptr(Pd), Pd.shape[0], Pd.shape[1], int(k), r.ctypes.data_as(ctypes.c_void_p),
+                                _ptr(C), _ptr(idx), _stream(torch, stream)))
+    return C, idx
+
+
+def bounded_assign(P, C, lo, hi, stream=None):
+    """Capacity-bounded assignment: (label int32 [n], count int64 [k]) device
+    tensors and the number of proposal rounds."""
+    import torch
+    load()
+    Pd, Cd = _dev(P, torch), _dev(C, torch)
+    n, k = Pd.shape[0], Cd.shape[0]
+    label = torch.empty(n, dtype=torch.int32, device="cuda")
+    count = torch.empty(k, dtype=torch.int64, device="cuda")
+    rounds = ctypes.c_int32()
+    _check(_lib.lma_bounded_assign(_ptr(Pd), n, Pd.shape[1], _ptr(Cd), k, int(lo), int(hi), _ptr(label),
+                                   _ptr(count), ctypes.byref(rounds), _stream(torch, stream)))
+    return label, count, int(rounds.value)
+
+
+def partition(X, M, lo, hi, iters, rand, U=None, stream=None):
+    """Block partition (lma_partition): dict with perm, u_perm (device int64),
+    block_ptr, u_block_ptr (numpy int64) and centres [M, d] in block order."""
+    import torch
+    load()
+    Xd = _dev(X, torch)
+    n, d = Xd.shape
+    Ud = _dev(U, torch) if U is not None else None
+    n_u = 0 if Ud is None else Ud.shape[0]
+    r = np.ascontiguousarray(np.asarray(rand, dtype=np.uint32))
+    if r.shape != (M,):
+        raise ValueError("rand must hold M values")
+    perm = torch.empty(n, dtype=torch.int64, device="cuda")
+    u_perm = torch.empty(n_u, dtype=torch.int64, device="cuda")
+    bp = np.zeros(M + 1, dtype=np.int64)
+    ubp = np.zeros(M + 1, dtype=np.int64)
+    cen = torch.empty((M, d), dtype=torch.float64, device="cuda")
+    _check(_lib.lma_partition(_ptr(Xd), n, _ptr(Ud) if Ud is not None else None, n_u, d, int(M), int(lo), int(hi),
+                              int(iters), r.ctypes.data_as(ctypes.c_void_p), _ptr(perm),
+                              bp.ctypes.data_as(ctypes.c_void_p), _ptr(u_perm) if n_u else None,
+                              ubp.ctypes.data_as(ctypes.c_void_p), _ptr(cen), _stream(torch, stream)))
+    return dict(perm=perm, block_ptr=bp, u_perm=u_perm, u_block_ptr=ubp, centres=cen)

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblma.so")
 SOURCES = ["engine.hip", "kernels_misc.hip", "vecsolve.hip", "grad.hip", "kvec.hip", "lma.hip", "lma_grad.hip", "ds.hip",
-           "kmeans.hip"]
+           "kmeans.hip", "partition.hip"]
 ARCH = os.environ.get("LMA_OFFLOAD_ARCH", "gfx950")
 
 
