@@ -84,43 +84,120 @@ def measured_traffic(kernel_mode):
     return rec["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(p, budget_s=25.0):
-    """The oracle timed on a bounded sample: support part (L_SS, V over all of
-    D and U) plus a spread of windows, scaled to all M windows by their cubic
-    cost model."""
-    from oracle import lma as olma
+def blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()]))
     except Exception:
-        cores = os.cpu_count()
+        return int(os.cpu_count())
+
+
+def window_cost(p):
+    """Cubic cost model of each window of the oracle: factor, support and
+    output right-hand sides, test right-hand sides."""
     J, _ = window_sizes(p)
-    u = np.diff(p.u_block_ptr).astype(np.float64)
-    cost = J ** 3 / 3 + J ** 2 * (2 * p.s + 1) + np.array(
+    u = np.diff(p.u_block_ptr).astype(np.float64) if p.U is not None else np.zeros(p.M)
+    return J ** 3 / 3 + J ** 2 * (2 * p.s + 1) + np.array(
         [J[m] ** 2 * u[m:min(m + p.B, p.M - 1) + 1].sum() for m in range(p.M)])
+
+
+def spread(p, k=16):
+    """k windows spread over the range of window sizes."""
+    J, _ = window_sizes(p)
+    order = np.argsort(J, kind="stable")
+    return sorted(set(int(m) for m in order[np.linspace(0, p.M - 1, min(k, p.M)).astype(int)]))
+
+
+def oracle_run(p, windows):
+    """The float64 oracle's fit + predict over the given windows, timed: the
+    support part (L_SS, V over all training and test points), each window, and
+    the global solve with the predictive combine."""
+    from oracle import lma as olma
     t0 = time.perf_counter()
     f = olma.Fit(p, windows=[], test=True)
     t_setup = time.perf_counter() - t0
-    order = np.argsort(J)
-    picks = list(order[np.linspace(0, p.M - 1, 16).astype(int)])
-    done, t_win = [], 0.0
-    for m in picks:
+    t_win = {}
+    for m in windows:
         t1 = time.perf_counter()
         f.window(int(m))
-        t_win += time.perf_counter() - t1
-        done.append(int(m))
-        if t_setup + t_win > budget_s:
-            break
+        t_win[int(m)] = time.perf_counter() - t1
     t1 = time.perf_counter()
     f.finish()
-    f.predict()
+    mean, var = f.predict()
     t_fin = time.perf_counter() - t1
-    est = t_setup + t_fin + t_win * cost.sum() / cost[done].sum()
-    return {"value": est, "unit": "s", "cores": int(cores), "kind": "oracle",
-            "sample": f"float64 oracle (whitened windows): support factorisation and V for all "
-                      f"{p.n} + {p.n_u} points, then {len(done)} of {p.M} windows with their test "
-                      f"right-hand sides ({t_win:.1f} s), scaled to all windows by "
-                      f"J^3/3 + J^2 (2|S|+1+u) cost; measured {t_setup + t_win + t_fin:.1f} s"}
+    return t_setup, t_win, t_fin, (mean, var)
+
+
+def estimate(p, t_setup, t_win, t_fin, picks):
+    cost = window_cost(p)
+    return t_setup + t_fin + sum(t_win[m] for m in picks) * cost.sum() / cost[picks].sum()
+
+
+def cpu_baseline(p, p_small=None, p_grad=None):
+    """The float64 oracle on the host's cores, in three parts:
+    value: fit + predict at the benchmark shape, from the support part and a
+    spread of 16 windows (with their test right-hand sides), scaled to all
+    windows by the cubic cost model;
+    complete_n65536: a complete fit + predict at the n=65536 workload, with
+    the same estimate formed from its own 16 spread windows beside it, which
+    checks the scaling;
+    lml_grad: one complete LML + gradient evaluation at a stated shape."""
+    cores = blas_threads()
+    picks = spread(p)
+    t_setup, t_win, t_fin, _ = oracle_run(p, picks)
+    est = estimate(p, t_setup, t_win, t_fin, picks)
+    out = {"value": est, "unit": "s", "cores": cores, "kind": "oracle",
+           "sample": f"float64 oracle (whitened windows): support factorisation and V for all {p.n} + {p.n_u} "
+                     f"points ({t_setup:.1f} s), then {len(picks)} of {p.M} windows spread over the window sizes, "
+                     f"with their test right-hand sides ({sum(t_win.values()):.1f} s), and the global solve and "
+                     f"combine ({t_fin:.1f} s); windows scaled to all {p.M} by J^3/3 + J^2 (2|S|+1+u)"}
+    if p_small is not None:
+        t0 = time.perf_counter()
+        ts, tw, tf, _ = oracle_run(p_small, range(p_small.M))
+        complete = time.perf_counter() - t0
+        pk = spread(p_small)
+        out["complete_n65536"] = {
+            "workload": f"fit+predict, n={p_small.n}, d={p_small.d}, M={p_small.M}, B={p_small.B}, "
+                        f"|S|={p_small.s}, n_u={p_small.n_u}",
+            "s": complete, "estimate_from_16_windows_s": estimate(p_small, ts, tw, tf, pk), "cores": cores}
+    if p_grad is not None:
+        from oracle import lma as olma
+        t0 = time.perf_counter()
+        olma.lml_grad(p_grad)
+        out["lml_grad"] = {"workload": f"LML+gradient, n={p_grad.n}, d={p_grad.d}, M={p_grad.M}, B={p_grad.B}, "
+                                       f"|S|={p_grad.s}", "s_per_eval": time.perf_counter() - t0, "cores": cores}
+    return out
+
+
+def oracle_errors(name, p, outs):
+    """Each mode's outputs against the stored float64 oracle vectors of this
+    workload (tests/golden, written by the oracle only): relative 2-norm,
+    largest element error over the largest element, largest element error
+    over the element itself (floor 1e-12 of the largest), and the LML's
+    relative error."""
+    jp = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.json")
+    npz = os.path.join(ROOT, "tests", "golden", f"{name}_oracle.npz")
+    if not (os.path.exists(jp) and os.path.exists(npz)):
+        return None
+    with open(jp) as f:
+        gold = json.load(f)
+    dg = p.digest()
+    for k, v in gold["digest"].items():
+        if (abs(dg[k] - v) > 1e-9 * max(1.0, abs(v))) if isinstance(v, float) else dg[k] != v:
+            return {"error": f"stored oracle values are for other inputs ({k})"}
+    z = np.load(npz)
+
+    def meas(a, b):
+        err = np.abs(a - b)
+        sc = np.max(np.abs(b))
+        return {"rel2": float(np.linalg.norm(a - b) / np.linalg.norm(b)), "rel_inf": float(np.max(err) / sc),
+                "elem": float(np.max(err / (np.abs(b) + 1e-12 * sc)))}
+
+    res = {"oracle": f"tests/golden/{name}_oracle.npz (float64 oracle, complete vectors)"}
+    for prec, (mean, var, lml_val) in outs.items():
+        res[prec] = {"mean": meas(mean, z["mean"]), "var": meas(var, z["var"]),
+                     "lml": abs(lml_val - gold["lml"]) / abs(gold["lml"])}
+    return res
 
 
 def main():
@@ -135,8 +212,9 @@ def main():
     ap.add_argument("--grad-evals", type=int, default=1, help="timed LML+gradient evaluations per precision")
     ap.add_argument("--no-n131072", action="store_true",
                     help="skip the LML+gradient rate at the n=131072 hyperparameter-fitting workload")
-    ap.add_argument("--no-kmeans", action="store_true", help="skip the partitioner k-means timing")
-    ap.add_argument("--cpu-budget", type=float, default=25.0)
+    ap.add_argument("--no-partition", action="store_true", help="skip the partitioner timing")
+    ap.add_argument("--no-cpu-extra", action="store_true",
+                    help="cpu baseline: skip the complete n=65536 run and the LML+gradient run")
     ap.add_argument("--small", action="store_true", help="n=65536 workload (quick check)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB mebibytes (to scale HBM byte counters)")
@@ -266,23 +344,28 @@ def main():
             log(f"n=131072 {prec} LML+grad: " + ", ".join(f"{k}: {v['s_per_eval'] * 1e3:.0f} ms" for k, v in rec.items()))
         del X3, y3, S3
 
-    # partitioner k-means steps on the same points: 10 Lloyd rounds + final
-    # assignment, k = M centres started at seeded rows
-    km = None
-    if not args.no_kmeans:
+    # the block partition on the GPU (lma_partition: k-means++ seeding, 10 Lloyd
+    # rounds, block sizes bounded to the workload's, chain order, test blocks,
+    # permutations) of the same training and test points
+    part = None
+    if not args.no_partition:
         try:
-            C0 = p.X[np.sort(np.random.default_rng(14114510).choice(p.n, p.M, replace=False))]
-            lma.kmeans(X, C0, 1)
+            b = np.diff(p.block_ptr)
+            lo, hi = (1024, 3072) if not args.small else (int(b.min()), int(b.max()))
+            rand = np.random.default_rng(20150125).integers(0, 2 ** 32, size=p.M, dtype=np.uint64).astype(np.uint32)
+            lma.partition(X, p.M, lo, hi, 10, rand, U=U)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            lma.kmeans(X, C0, 10)
+            r = lma.partition(X, p.M, lo, hi, 10, rand, U=U)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t1
-            km = {"workload": f"k-means, n={p.n}, d={p.d}, k={p.M}, 10 Lloyd rounds + final assignment",
-                  "s": dt, "ms_per_round": dt / 10 * 1e3}
-            log(f"k-means: {dt * 1e3:.1f} ms")
+            sz = np.diff(r["block_ptr"])
+            part = {"workload": f"block partition, n={p.n} + n_u={p.n_u}, d={p.d}, M={p.M}, sizes in [{lo}, {hi}], "
+                                f"k-means++ seeding, 10 Lloyd rounds", "s": dt,
+                    "block_sizes": [int(sz.min()), int(sz.max())]}
+            log(f"partition: {dt * 1e3:.1f} ms")
         except Exception as e:  # reported, never fatal to the headline measurement
-            km = {"error": str(e)}
+            part = {"error": str(e)}
 
     f_fit, f_pred = algorithmic_flops(p)
     head = "fp64" if "fp64" in res else list(res)[0]
@@ -323,7 +406,7 @@ def main():
         "lml_evals_per_s_fp64": lml_rate,
         "lml_grad": grad_res or None,
         "lml_grad_n131072": grad3,
-        "partition_kmeans": km,
+        "partition": part,
         "alg_flops": {"fit": f_fit, "predict": f_pred},
         "roofline": roofline,
     }
@@ -333,11 +416,14 @@ def main():
         out["mixed"]["speedup_vs_fp64"] = res["fp64"]["s_per_step"] / res["mixed"]["s_per_step"]
         out["mixed"]["rel_err_vs_fp64"] = {"mean": r(a[0], b[0]), "var": r(a[1], b[1]),
                                            "lml": abs(a[2] - b[2]) / abs(b[2])}
+    out["err_vs_oracle"] = oracle_errors("cfg1" if args.small else "cfg2", p, outs)
     if "fp64" in outs and p.y_u is not None:
         out["rmse_fp64"] = float(np.sqrt(np.mean((outs["fp64"][0] - p.y_u) ** 2)))
     if not args.no_cpu:
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(p, budget_s=args.cpu_budget)
+        extra = not args.no_cpu_extra and not args.small
+        out["cpu_baseline"] = cpu_baseline(p, synth.make_config(1) if extra else None,
+                                           synth.make_sweep16k(512, 2) if extra else None)
         log(f"cpu baseline {time.perf_counter() - t0:.1f} s")
     print(json.dumps(out), flush=True)
 

@@ -4,8 +4,8 @@
  *
  * LMA needs the training and test inputs partitioned into M blocks, ordered
  * so that the B blocks after each one are its most correlated neighbours
- * (section "Low-Rank-cum-Markov Approximation"; the paper leaves the scheme
- * to a simple parallelised clustering method of earlier work).  The library
+ * (section "Low-Rank-cum-Markov Approximation"; the paper takes the
+ * clustering from earlier work and does not specify it).  The library
  * takes the partition as an input (block_ptr in lma.h); these entry points
  * compute one on the GPU: k-means++ seeding, Lloyd's iteration (nearest-centre
  * assignment and centre update), a capacity-bounded assignment that keeps

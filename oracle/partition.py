@@ -3,8 +3,8 @@ infrastructure only).
 
 LMA needs the training inputs D and the test inputs U partitioned into M
 blocks, with the blocks ordered so that the next B blocks of each are its most
-correlated neighbours (section "Low-Rank-cum-Markov Approximation": D and U are
-partitioned by a simple parallelised clustering scheme of earlier work, and
+correlated neighbours (section "Low-Rank-cum-Markov Approximation": the paper
+takes the clustering of D and U from earlier work without specifying it, and
 D^B_m is the set of the B blocks after D_m).  The partition computed here:
 
   1. seeding (k-means++, D^2 sampling): the first centre is point

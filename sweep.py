@@ -31,16 +31,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-SUPPORT_SEED = 20150125
-
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
 def nested_supports(X, sizes):
-    order = np.random.default_rng(SUPPORT_SEED).permutation(X.shape[0])
-    return {s: X[np.sort(order[:s])].copy() for s in sizes}
+    import synth
+    return {s: synth.nested_support(X, s) for s in sizes}
 
 
 def run_point(lma, torch, Xd, yd, Ud, p, S, B, log_hyp, reps, precision):
@@ -82,6 +80,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--reps", type=int, default=1, help="timed repetitions per point")
     ap.add_argument("--out", default="")
+    ap.add_argument("--sizes", default="", help="comma-separated |S| values (default: the workload's)")
+    ap.add_argument("--orders", default="", help="comma-separated Markov orders B (default: the workload's)")
     args = ap.parse_args()
 
     import torch
@@ -106,6 +106,10 @@ def main():
             log_hyp[-1] = np.log(1.01)
         else:
             raise SystemExit(f"unknown workload {wl}")
+        if args.sizes:
+            sizes = [int(v) for v in args.sizes.split(",")]
+        if args.orders:
+            Bs = [int(v) for v in args.orders.split(",")]
         log(f"{wl}: inputs drawn in {time.perf_counter() - t0:.1f} s (n={p.n} d={p.d} M={p.M} n_u={p.n_u})")
         dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
         Xd, yd, Ud = dev(p.X), dev(p.y), dev(p.U)

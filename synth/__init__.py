@@ -407,6 +407,26 @@ def make_config2(F=512, n=524288, M=256, n_u=65536, s=1024, B=3, sn2_model=0.01,
                    U=U, u_block_ptr=ubp, y_u=y_u, name="cfg2")
 
 
+SUPPORT_SEED = 20150125
+
+
+def nested_support(X, s, seed=SUPPORT_SEED):
+    """Support set of the |S| x B sweep: the first s rows (in index order) of
+    one seeded permutation of the training points, so that smaller support
+    sets are subsets of larger ones."""
+    order = np.random.default_rng(seed).permutation(X.shape[0])
+    return X[np.sort(order[:s])].copy()
+
+
+def make_sweep16k(s, B):
+    """The n=16384 workload of the |S| x B sweep: X ~ U[0,1]^8, GP-sample
+    outputs (l_i ~ logU[0.1, 1], sf2=1, sn2=0.05), M=16 k-means blocks of 1024,
+    4096 test points; support set of size s from nested_support; Markov order
+    B (B = 15 = M-1 is the full GP)."""
+    p = make_uniform_kmeans(1, 16384, 8, 16, B, 16, 4096, 0.05, name=f"n16384_S{s}_B{B}")
+    return p.with_(S=nested_support(p.X, s))
+
+
 def make_config(k: int, **kw) -> Problem:
     return {0: make_config0, 1: make_config1, 2: make_config2, 3: make_config3}[k](**kw)
 

@@ -1,14 +1,20 @@
 """Write the stored expected values for the full-size parity tests.
 
 Calls only the CPU oracle (oracle/) on inputs drawn by synth/; nothing here
-touches the GPU library.  For each workload it stores a digest of the drawn
-inputs (so a test can tell that it regenerated the same problem), the log
-marginal likelihood, and the predictive mean and variance at a fixed sample
-of test points.  For the likelihood-gradient workload (cfg3: n=131072, d=8,
-M=128, B=2, |S|=512, no test set) it stores the log marginal likelihood and
-its gradient in (log l, log sigma_s^2, log sigma_n^2) from the oracle's adjoint.
+touches the GPU library.  For each prediction workload it stores a digest of
+the drawn inputs (so a test can tell that it regenerated the same problem) and
+the log marginal likelihood in <name>_oracle.json, and the complete predictive
+mean and variance vectors in <name>_oracle.npz.  For the likelihood-gradient
+workload (cfg3: n=131072, d=8, M=128, B=2, |S|=512, no test set) it stores the
+log marginal likelihood and its gradient in (log l, log sigma_s^2,
+log sigma_n^2) from the oracle's adjoint.
 
-    python tests/golden/make_golden.py cfg1 cfg2 cfg3
+Workloads: cfg0 (n=2048), cfg1 (n=65536), cfg2 (n=524288, the benchmark
+shape), cfg3 (gradient), and two extremes of the |S| x B sweep at n=16384:
+sweep_B15 (M=16, B=15 = M-1: one window of all 16384 points, |S|=1024) and
+sweep_S2048 (|S|=2048, B=2).
+
+    python tests/golden/make_golden.py cfg0 cfg1 cfg2 cfg3 sweep_B15 sweep_S2048
 """
 import json
 import os
@@ -24,12 +30,10 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 from oracle import lma as olma  # noqa: E402
 
-SAMPLE = 1024
-
-
-def sample_index(n_u, k=SAMPLE):
-    rng = np.random.default_rng(20150125)
-    return np.sort(rng.choice(n_u, size=min(k, n_u), replace=False))
+PREDICT = {"cfg0": lambda: synth.make_config(0), "cfg1": lambda: synth.make_config(1),
+           "cfg2": lambda: synth.make_config(2),
+           "sweep_B15": lambda: synth.make_sweep16k(1024, 15),
+           "sweep_S2048": lambda: synth.make_sweep16k(2048, 2)}
 
 
 def make_grad(name, k):
@@ -56,32 +60,31 @@ def make_grad(name, k):
 def make(name):
     if name == "cfg3":
         return make_grad(name, 3)
-    k = {"cfg0": 0, "cfg1": 1, "cfg2": 2}[name]
     t0 = time.time()
-    p = synth.make_config(k)
+    p = PREDICT[name]()
     print(f"{name}: inputs drawn in {time.time() - t0:.1f} s", flush=True)
     t0 = time.time()
     r = olma.fit_predict(p)
-    print(f"{name}: oracle fit+predict in {time.time() - t0:.1f} s", flush=True)
-    idx = sample_index(p.n_u)
+    dt = time.time() - t0
+    print(f"{name}: oracle fit+predict in {dt:.1f} s", flush=True)
     out = {
         "workload": name,
         "source": "oracle.lma.fit_predict (float64, whitened windows)",
         "digest": p.digest(),
         "lml": r["lml"],
-        "sample_index": idx.tolist(),
-        "mean": r["mean"][idx].tolist(),
-        "var": r["var"][idx].tolist(),
         "mean_norm": float(np.linalg.norm(r["mean"])),
         "var_norm": float(np.linalg.norm(r["var"])),
         "rmse": float(np.sqrt(np.mean((r["mean"] - p.y_u) ** 2))) if p.y_u is not None else None,
+        "oracle_seconds": dt,
+        "oracle_threads": os.cpu_count(),
     }
     path = os.path.join(HERE, f"{name}_oracle.json")
     with open(path, "w") as f:
         json.dump(out, f)
-    print(f"wrote {path}", flush=True)
+    np.savez_compressed(os.path.join(HERE, f"{name}_oracle.npz"), mean=r["mean"], var=r["var"])
+    print(f"wrote {path} and the .npz vectors", flush=True)
 
 
 if __name__ == "__main__":
-    for nm in sys.argv[1:] or ["cfg1", "cfg2"]:
+    for nm in sys.argv[1:] or ["cfg0", "cfg1"]:
         make(nm)
