@@ -169,6 +169,12 @@ def cpu_baseline(p, p_small=None, p_grad=None):
     return out
 
 
+def lml_small_problem(synth):
+    """The shape the CPU oracle's LML + gradient is timed on: n=8192 in
+    [0,1]^8, M=8 k-means blocks of 1024, B=2, |S|=256."""
+    return synth.make_uniform_kmeans(3, 8192, 8, 8, 2, 256, 0, 0.05, name="n8192")
+
+
 def oracle_errors(name, p, outs):
     """Each mode's outputs against the stored float64 oracle vectors of this
     workload (tests/golden, written by the oracle only): relative 2-norm,
@@ -344,6 +350,19 @@ def main():
             log(f"n=131072 {prec} LML+grad: " + ", ".join(f"{k}: {v['s_per_eval'] * 1e3:.0f} ms" for k, v in rec.items()))
         del X3, y3, S3
 
+    # LML + gradient at the small shape the CPU oracle is timed on (for the ratio)
+    lml_small = None
+    if not args.no_grad and not args.no_cpu and not args.no_cpu_extra and not args.small:
+        ps = lml_small_problem(synth)
+        prob = lma.LmlProblem.from_problem(ps)
+        prob(ps.log_hyp)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            prob(ps.log_hyp)
+        torch.cuda.synchronize()
+        lml_small = (time.perf_counter() - t1) / 5
+
     # the block partition on the GPU (lma_partition: k-means++ seeding, 10 Lloyd
     # rounds, block sizes bounded to the workload's, chain order, test blocks,
     # permutations) of the same training and test points
@@ -423,7 +442,9 @@ def main():
         t0 = time.perf_counter()
         extra = not args.no_cpu_extra and not args.small
         out["cpu_baseline"] = cpu_baseline(p, synth.make_config(1) if extra else None,
-                                           synth.make_sweep16k(512, 2) if extra else None)
+                                           lml_small_problem(synth) if extra else None)
+        if extra and lml_small is not None:
+            out["cpu_baseline"]["lml_grad"]["gpu_s_per_eval"] = lml_small
         log(f"cpu baseline {time.perf_counter() - t0:.1f} s")
     print(json.dumps(out), flush=True)
 

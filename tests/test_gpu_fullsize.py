@@ -16,9 +16,12 @@ Measures, per output vector a against the oracle's b:
   elem = max_i |a_i - b_i| / (|b_i| + 1e-12 max_j |b_j|) (each element against
          itself).
 Bars: rel2 and rel_inf <= 1e-9 in float64 and <= 1e-4 in mixed precision;
-elem is reported (an element near zero carries the absolute error of its
-larger neighbours, so elem is not bounded by the vector bars).  The log
-marginal likelihood: |a - b| / |b| under the vector bars."""
+elem <= 1e-5 in float64 and <= 1e-3 in mixed precision.  An element near zero
+carries the absolute error of its larger neighbours: the predictive means
+cross zero, and their smallest elements are 1e-4 to 1e-5 of the largest, so
+an error at the scale of the vector (rel_inf) shows up to ~1e4 times larger
+in elem; measured worst cases 4.8e-7 (float64) and 6.2e-5 (mixed), both in the
+mean.  The log marginal likelihood: |a - b| / |b| under the vector bars."""
 import json
 import os
 
@@ -30,6 +33,7 @@ import synth
 pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 TOL = {"fp64": 1e-9, "mixed": 1e-4}
+ELEM = {"fp64": 1e-5, "mixed": 1e-3}
 WORKLOADS = {
     "cfg0": lambda: synth.make_config(0),
     "cfg1": lambda: synth.make_config(1),
@@ -86,5 +90,5 @@ def test_fullsize_against_stored_oracle(lib, name):
         print(f"  mean {em}\n  var {ev}\n  lml {el:.2e}", flush=True)
         tol = TOL[prec]
         for e in (em, ev):
-            assert e["rel2"] <= tol and e["rel_inf"] <= tol
+            assert e["rel2"] <= tol and e["rel_inf"] <= tol and e["elem"] <= ELEM[prec]
         assert el <= tol
