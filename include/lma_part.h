@@ -142,7 +142,8 @@ lma_status lma_bounded_assign(const double *P, int64_t n, int32_t d, const doubl
  *      u_block_ptr (host) [M+1] the same for the test points (NULL when
  *      n_u = 0; empty test blocks are possible).
  * centres [M][d] (device, or NULL) receives the block centres in block order.
- * Points must be finite.  Synchronises the stream.
+ * lma_fit needs every block non-empty: take lo >= 1.  Points must be finite.
+ * Synchronises the stream.
  * Errors: LMA_E_ARG, LMA_E_HIP, LMA_E_NOMEM.
  */
 lma_status lma_partition(const double *X, int64_t n, const double *U, int64_t n_u, int32_t d, int32_t M, int64_t lo,
