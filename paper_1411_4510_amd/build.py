@@ -15,6 +15,10 @@ LIB = os.path.join(HERE, "liblma.so")
 SOURCES = ["engine.hip", "kernels_misc.hip", "vecsolve.hip", "grad.hip", "kvec.hip", "lma.hip", "lma_grad.hip", "ds.hip",
            "kmeans.hip", "partition.hip"]
 ARCH = os.environ.get("LMA_OFFLOAD_ARCH", "gfx950")
+# Per-source flags.  kvec.hip: its MFMA accumulators feed vector arithmetic
+# right after every short k loop; in the accumulator-register form the compiler
+# copies them between register files on every iteration, the VGPR form does not.
+SOURCE_FLAGS = {"kvec.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def hipcc():
@@ -38,7 +42,7 @@ def build(verbose=False, jobs=3):
     for src in SOURCES:
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [cc] + flags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc] + flags + SOURCE_FLAGS.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -3,8 +3,9 @@
 // One workgroup (4 wave64) per item: the item's row coordinates stay in LDS,
 // each column tile is staged in LDS in turn, the cross products x_r . x_c come
 // from v_mfma_f64_16x16x4f64 (wave (wr, wc) owns a 64 x 64 quadrant as 4 x 4
-// sub-tiles; lane l supplies row l%16 and coordinate k4 + l/16 of a 4-wide
-// step), and the epilogue forms d^2 = |x_r|^2 + |x_c|^2 - 2 x_r . x_c (all
+// sub-tiles, taken one 16-column strip at a time so that few accumulators are
+// live and two workgroups fit on a CU; lane l supplies row l%16 and coordinate
+// k4 + l/16 of a 4-wide step), and the epilogue forms d^2 = |x_r|^2 + |x_c|^2 - 2 x_r . x_c (all
 // coordinates taken relative to the item's first row point), the
 // covariance and its products with the column vectors, accumulated per row in
 // registers.  Row sums are reduced in a fixed order (lane shuffles, then the
@@ -70,10 +71,9 @@ __global__ __launch_bounds__(256) void k_kvec(KvArgs a) {
   for (int c = it.c0; c < it.c1; ++c) {
     const KvCol col = a.cols[c];
     __syncthreads();  // the previous column tile is consumed
-    for (int idx = tid; idx < TB * dp; idx += NT) {
-      const int r = idx / dp, k = idx - r * dp;
-      xc[r * ldx + k] = (r < col.nc && k < d) ? col.x[(int64_t)r * d + k] - org[k] : 0.0;
-    }
+    for (int r = tid >> 1; r < TB; r += NT / 2)
+      for (int k = tid & 1; k < dp; k += 2)
+        xc[r * ldx + k] = (r < col.nc && k < d) ? col.x[(int64_t)r * d + k] - org[k] : 0.0;
     if (tid < TB) {
       cv0[tid] = (col.v0 && tid < col.nc) ? col.v0[tid] : 0.0;
       cv1[tid] = (col.v1 && tid < col.nc) ? col.v1[tid] : 0.0;
@@ -84,23 +84,23 @@ __global__ __launch_bounds__(256) void k_kvec(KvArgs a) {
       for (int k = 0; k < dp; ++k) s += xc[tid * ldx + k] * xc[tid * ldx + k];
       nrm_c[tid] = s;
     }
-    dv4 acc[4][4];
-    zero_acc<double>(acc);
-    for (int k4 = 0; k4 < dp; k4 += 4) {
-      double af[4], bf[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        af[t] = xr[(wr * 64 + t * 16 + (lane & 15)) * ldx + k4 + (lane >> 4)];
-        bf[t] = xc[(wc * 64 + t * 16 + (lane & 15)) * ldx + k4 + (lane >> 4)];
-      }
-#pragma unroll
-      for (int ra = 0; ra < 4; ++ra)
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb) acc[ra][rb] = Mfma<double>::op(af[ra], bf[rb], acc[ra][rb]);
-    }
     __syncthreads();  // column norms written
-#pragma unroll
+    // one 16-column strip at a time: its 4 product tiles, then their covariance
+    // entries (keeps 16 accumulators live instead of 64)
+#pragma unroll 1
     for (int rb = 0; rb < 4; ++rb) {
+      dv4 acc[4];
+#pragma unroll
+      for (int ra = 0; ra < 4; ++ra) acc[ra] = Mfma<double>::op(0.0, 0.0, dv4{0.0, 0.0, 0.0, 0.0});
+      const int cb = (wc * 64 + rb * 16 + (lane & 15)) * ldx + (lane >> 4);
+      for (int k4 = 0; k4 < dp; k4 += 4) {
+        const double bf = xc[cb + k4];
+#pragma unroll
+        for (int ra = 0; ra < 4; ++ra) {
+          const double af = xr[(wr * 64 + ra * 16 + (lane & 15)) * ldx + k4 + (lane >> 4)];
+          acc[ra] = Mfma<double>::op(af, bf, acc[ra]);
+        }
+      }
       const int cc = wc * 64 + rb * 16 + (lane & 15);
       const double nc = nrm_c[cc], v0 = cv0[cc], v1 = cv1[cc];
 #pragma unroll
@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256) void k_kvec(KvArgs a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int rr = wr * 64 + ra * 16 + Mfma<double>::row(lane, v);
-          double d2 = nrm_r[rr] + nc - 2.0 * acc[ra][rb][v];
+          double d2 = nrm_r[rr] + nc - 2.0 * acc[ra][v];
           d2 = d2 > 0.0 ? d2 : 0.0;
           const double kv = sf2 * exp(-0.5 * d2);
           s0[ra][v] += kv * v0;

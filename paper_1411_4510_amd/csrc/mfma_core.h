@@ -183,7 +183,7 @@ __device__ inline void zero_acc(typename Mfma<Tc>::acc (&acc)[4][4]) {
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (typename Mfma<Tc>::acc){Tc(0), Tc(0), Tc(0), Tc(0)};
+    for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<Tc>::op(Tc(0), Tc(0), (typename Mfma<Tc>::acc){Tc(0), Tc(0), Tc(0), Tc(0)});
 }
 
 
