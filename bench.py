@@ -70,8 +70,8 @@ def measured_traffic(kernel_mode):
     """HBM bytes per k_update launch from the committed PMC runs, if the kernel
     source has not changed since they were taken (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_update_fp64_n524288_traffic.json")
-    if kernel_mode != "fp64" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", f"k_update_{kernel_mode}_n524288_traffic.json")
+    if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
@@ -116,15 +116,19 @@ def oracle_run(p, windows):
     t0 = time.perf_counter()
     f = olma.Fit(p, windows=[], test=True)
     t_setup = time.perf_counter() - t0
+    log(f"oracle n={p.n}: support part {t_setup:.1f} s")
     t_win = {}
-    for m in windows:
+    for k, m in enumerate(windows):
         t1 = time.perf_counter()
         f.window(int(m))
         t_win[int(m)] = time.perf_counter() - t1
+        if k % 8 == 7:
+            log(f"oracle n={p.n}: {k + 1} of {len(windows)} windows")
     t1 = time.perf_counter()
     f.finish()
     mean, var = f.predict()
     t_fin = time.perf_counter() - t1
+    log(f"oracle n={p.n}: global solve and prediction {t_fin:.1f} s")
     return t_setup, t_win, t_fin, (mean, var)
 
 
@@ -164,6 +168,7 @@ def cpu_baseline(p, p_small=None, p_grad=None):
         from oracle import lma as olma
         t0 = time.perf_counter()
         olma.lml_grad(p_grad)
+        log(f"oracle LML+gradient n={p_grad.n}: {time.perf_counter() - t0:.1f} s")
         out["lml_grad"] = {"workload": f"LML+gradient, n={p_grad.n}, d={p_grad.d}, M={p_grad.M}, B={p_grad.B}, "
                                        f"|S|={p_grad.s}", "s_per_eval": time.perf_counter() - t0, "cores": cores}
     return out

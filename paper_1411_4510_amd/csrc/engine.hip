@@ -25,12 +25,53 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
 
   typename Mfma<TK>::acc accv[4][4];   // V_i V_j^T
   typename Mfma<T>::acc accl[4][4];    // sum_k L_ik L_jk^T (aliases accv when not MIXED)
-  zero_acc<TK>(accv);
+  const bool band = ri.src == SRC_BAND;    // V part already inside the band entries
+  const bool tband = ri.src == SRC_TBAND;  // likewise for test rows
+  if (band || tband) {
+    // Band rows start from minus their residual entries, so that the band reads
+    // are in flight with the first operand loads instead of after the k loop;
+    // the epilogue then stores -(accumulator).  Every lane issues its 64 reads
+    // unconditionally (padding rows and columns read a valid entry of the tile and
+    // are masked to zero), and the accumulators are started through an MFMA, as
+    // in zero_acc, so that they stay in their register file.
+    const int nvr = ri.nvalid, nvc = rj.nvalid;
+    int64_t rowp[4][4], rowb[4][4], colq[4], colb[4];
+#pragma unroll
+    for (int cs = 0; cs < 4; ++cs) {
+      const int col = wc * 64 + cs * 16 + (lane & 15);
+      colq[cs] = rj.pt0 + (col < nvc ? col : nvc - 1);
+      colb[cs] = tband ? 0 : a.brow[colq[cs]];
+    }
+#pragma unroll
+    for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = wr * 64 + rs * 16 + Mfma<TK>::row(lane, v);
+        rowp[rs][v] = ri.pt0 + (row < nvr ? row : nvr - 1);
+        rowb[rs][v] = a.brow[rowp[rs][v]];
+      }
+#pragma unroll
+    for (int rs = 0; rs < 4; ++rs)
+#pragma unroll
+      for (int cs = 0; cs < 4; ++cs) {
+        typename Mfma<TK>::acc r0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = wr * 64 + rs * 16 + Mfma<TK>::row(lane, v);
+          const int col = wc * 64 + cs * 16 + (lane & 15);
+          const int64_t p = rowp[rs][v], q = colq[cs];
+          const int64_t e = (tband || q <= p) ? rowb[rs][v] + q : colb[cs] + p;
+          const TK kv = (TK)a.band[e];
+          r0[v] = (row < nvr && col < nvc) ? -kv : TK(0);
+        }
+        accv[rs][cs] = Mfma<TK>::op(TK(0), TK(0), r0);
+      }
+  } else {
+    zero_acc<TK>(accv);
+  }
   if constexpr (MIXED) zero_acc<T>(accl);
   const TK* vi = MIXED ? (const TK*)ri.vt64 : (const TK*)ri.vt;
   const TK* vj = MIXED ? (const TK*)rj.vt64 : (const TK*)rj.vt;
-  const bool band = ri.src == SRC_BAND;    // V part already inside the band entries
-  const bool tband = ri.src == SRC_TBAND;  // likewise for test rows
   if (!band && !tband && vi != nullptr && vj != nullptr && a.vlen > 0)
     wave_gemm<TK, TK>(accv, vi, a.vld, ri.nvalid, vj, a.vld, rj.nvalid, 0, a.vlen, wr * 64, wc * 64, lane);
   // factor columns kb .. j-1 (a row is zero left of its kbeg)
@@ -105,11 +146,8 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
           if (kern) {
             kv = sf2 * k_exp(TK(-0.5) * sq[rs][cs][v]);
             if (diag && row == col) kv += sn2;
-          } else if (band) {
-            const int64_t p = ri.pt0 + row, q = rj.pt0 + col;
-            kv = (TK)(q <= p ? a.band[a.brow[p] + q] : a.band[a.brow[q] + p]);
-          } else if (tband) {
-            kv = (TK)a.band[a.brow[ri.pt0 + row] + rj.pt0 + col];
+          } else if (band || tband) {
+            kv = TK(0);  // the residual entry started the accumulator (negated)
           } else if (ri.src == SRC_EXPLICIT) {
             kv = (TK)ri.expl[(int64_t)row * ri.eld + (int64_t)a.j * TB + col];
           } else {
@@ -139,48 +177,124 @@ __global__ __launch_bounds__(NT) void k_update(StepArgs<T> a) {
 // float32 window factors of the mixed mode included): the diagonal tiles of
 // late column steps hold Schur complements near the noise level, and their
 // factor and inverse feed every later tile.
+//
+// Both run on 32 x 32 blocks.  Factor, for each block column kb: one wave
+// factors the diagonal block in lock step (no workgroup barrier per column),
+// the rows below are solved against it one row per thread, and the trailing
+// block update is spread over the workgroup.  Inverse (in place, X = L^-1):
+// the four diagonal blocks are inverted by the four waves at once, then block
+// columns right to left: T_ib = sum_{k=jb+1..ib} X_ib,k L_k,jb for every block
+// row ib below jb, and X_ib,jb = -T_ib X_jb,jb.  About twenty workgroup
+// barriers per tile instead of two per column.
+constexpr int DB = 32;          // block size of the diagonal-tile algorithms
+constexpr int DNB = TB / DB;    // blocks per tile side
+constexpr int DT_LD = DB + 1;   // row stride of the block products' scratch
+
+__device__ inline void wave_sync_lds() {
+  // LDS writes of this wave are visible to its other lanes after this point
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T>
 __global__ __launch_bounds__(NT) void k_diag(StepArgs<T> a, const int32_t* __restrict__ plist) {
   typedef double TA;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TA* A = reinterpret_cast<TA*>(smem_raw);  // [TB][DIAG_LD]
-  TA* col0 = A + TB * DIAG_LD;              // [TB] double-buffered column copies
-  TA* col1 = col0 + TB;
-  TA* part = col1 + TB;                     // [2][TB] partial dot products
+  TA* Tt = A + TB * DIAG_LD;                // [DNB-1][DB][DT_LD] block products
   __shared__ int bad;
   __shared__ double lsum[NT / 64];
   const int p = plist[blockIdx.x];
   const ProbDesc pd = a.pd[p];
   const RowTile<T> rj = a.rt[pd.first + a.j];
   T* src = rj.panel + (int64_t)a.j * TB;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) bad = 0;
   for (int idx = tid; idx < TB * TB; idx += NT) {
     const int r = idx >> 7, c = idx & (TB - 1);
     A[r * DIAG_LD + c] = c <= r ? (TA)src[(int64_t)r * rj.ld + c] : TA(0);
   }
   __syncthreads();
-  // Right-looking factorisation; the column scaling of step k runs
-  // concurrently with the trailing update of step k+1 (disjoint columns).
-  const int tr = tid >> 4, tc = tid & 15;
-  for (int k = 0; k < TB; ++k) {
-    TA dkk = A[k * DIAG_LD + k];
-    const bool ok = dkk > TA(0);
-    if (!ok) dkk = TA(1);
-    const TA rinv = TA(1) / dkk;
-    for (int r = k + 1 + tr; r < TB; r += 16) {
-      const TA lrk = A[r * DIAG_LD + k] * rinv;
-      for (int c = k + 1 + tc; c <= r; c += 16) A[r * DIAG_LD + c] -= lrk * A[c * DIAG_LD + k];
+
+  // ---- factor
+  for (int kb = 0; kb < DNB; ++kb) {
+    const int b0 = kb * DB;
+    if (w == 0) {  // diagonal block, right-looking, one wave in lock step
+      const int rl = lane & 31, h = lane >> 5, r = b0 + rl;
+      for (int k = 0; k < DB; ++k) {
+        const int kk = b0 + k;
+        TA dkk = A[kk * DIAG_LD + kk];
+        const bool ok = dkk > TA(0);
+        if (!ok) dkk = TA(1);
+        const TA piv = k_sqrt(dkk), ip = TA(1) / piv;
+        wave_sync_lds();  // every lane has read the pivot
+        if (h == 0) {
+          if (rl > k) {
+            A[r * DIAG_LD + kk] *= ip;
+          } else if (rl == k) {
+            A[kk * DIAG_LD + kk] = piv;
+            if (!ok) bad = 1;
+          }
+        }
+        wave_sync_lds();  // column kk scaled
+        if (rl > k) {
+          const TA lrk = A[r * DIAG_LD + kk];
+          for (int c = kk + 1 + h; c <= r; c += 2) A[r * DIAG_LD + c] -= lrk * A[c * DIAG_LD + kk];
+        }
+        wave_sync_lds();
+      }
     }
     __syncthreads();
-    const TA piv = k_sqrt(dkk), ip = TA(1) / piv;
-    for (int r = k + 1 + tid; r < TB; r += NT) A[r * DIAG_LD + k] *= ip;
-    if (tid == 0) {
-      A[k * DIAG_LD + k] = piv;
-      if (!ok) bad = 1;
+    const int m = TB - b0 - DB;  // rows below the block
+    if (m == 0) break;
+    if (tid < m) {  // rows below: solve x L_kb^T = a, one row per thread
+      const int r = b0 + DB + tid;
+      TA x[DB];
+#pragma unroll
+      for (int c = 0; c < DB; ++c) x[c] = A[r * DIAG_LD + b0 + c];
+#pragma unroll
+      for (int c = 0; c < DB; ++c) {
+        TA sacc = x[c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) sacc -= x[k] * A[(b0 + c) * DIAG_LD + b0 + k];
+        x[c] = sacc / A[(b0 + c) * DIAG_LD + b0 + c];
+      }
+#pragma unroll
+      for (int c = 0; c < DB; ++c) A[r * DIAG_LD + b0 + c] = x[c];
     }
+    __syncthreads();
+    // trailing update of the lower triangle below and right of the block, 4 x 4 per thread
+    const int m4 = m >> 2;
+    for (int t = tid; t < m4 * m4; t += NT) {
+      const int bi = t / m4, bj = t - bi * m4;
+      if (bj > bi) continue;
+      const int r0 = b0 + DB + 4 * bi, c0 = b0 + DB + 4 * bj;
+      TA acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = TA(0);
+      for (int k = 0; k < DB; ++k) {
+        TA ar[4], ac[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ar[u] = A[(r0 + u) * DIAG_LD + b0 + k];
+          ac[u] = A[(c0 + u) * DIAG_LD + b0 + k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] += ar[u] * ac[v];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (c0 + v <= r0 + u) A[(r0 + u) * DIAG_LD + c0 + v] -= acc[u][v];
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (bad && tid == 0) a.status[p] = 1;
   // store L_jj and its log-diagonal
   for (int idx = tid; idx < TB * TB; idx += NT) {
@@ -193,34 +307,54 @@ __global__ __launch_bounds__(NT) void k_diag(StepArgs<T> a, const int32_t* __res
     for (int o = 32; o > 0; o >>= 1) ls += __shfl_xor(ls, o);
     if ((tid & 63) == 0) lsum[tid >> 6] = ls;
   }
-  // in-place inverse of the lower-triangular factor, last column first:
-  //   X_jj = 1/L_jj,  X_{r,jj} = -X_jj * sum_{k=jj+1}^{r} X_rk L_{k,jj}
-  for (int r = tid; r < TB; r += NT) col0[r] = A[r * DIAG_LD + (TB - 1)];
-  __syncthreads();
+  __syncthreads();  // the factor is stored and read before the inverse overwrites it
   if (tid == 0) {
     const double tot = lsum[0] + lsum[1] + lsum[2] + lsum[3];
     a.logdiag[(int64_t)p * a.maxT + a.j] = (a.j >= pd.ld_from) ? tot : 0.0;
   }
-  for (int jj = TB - 1; jj >= 0; --jj) {
-    TA* cur = ((TB - 1 - jj) & 1) ? col1 : col0;  // old column jj (rows > jj valid)
-    TA* nxt = ((TB - 1 - jj) & 1) ? col0 : col1;
-    const TA xjj = TA(1) / A[jj * DIAG_LD + jj];     // not written before the next barrier
-    {
-      const int r = jj + 1 + (tid >> 1), h = tid & 1;
-      TA s = TA(0);
-      if (r < TB) {
-        for (int k = jj + 1 + h; k <= r; k += 2) s += A[r * DIAG_LD + k] * cur[k];
-        part[h * TB + r] = s;
-      }
+
+  // ---- inverse, diagonal blocks: wave w inverts block w, last column first:
+  //   X_jj = 1/L_jj,  X_ij = -X_jj sum_{k=j+1..i} X_ik L_kj
+  {
+    const int b0 = w * DB, il = lane & 31, h = lane >> 5;
+    for (int jj = DB - 1; jj >= 0; --jj) {
+      const TA xjj = TA(1) / A[(b0 + jj) * DIAG_LD + b0 + jj];
+      TA sacc = TA(0);
+      if (il > jj)
+        for (int k = jj + 1 + h; k <= il; k += 2) sacc += A[(b0 + il) * DIAG_LD + b0 + k] * A[(b0 + k) * DIAG_LD + b0 + jj];
+      sacc += __shfl_xor(sacc, 32);
+      wave_sync_lds();  // column jj of L read by every lane
+      if (h == 0 && il > jj) A[(b0 + il) * DIAG_LD + b0 + jj] = -xjj * sacc;
+      if (lane == 0) A[(b0 + jj) * DIAG_LD + b0 + jj] = xjj;
+      wave_sync_lds();
     }
-    __syncthreads();
-    for (int r = jj + 1 + tid; r < TB; r += NT) A[r * DIAG_LD + jj] = -xjj * (part[r] + part[TB + r]);
-    if (tid == 0) A[jj * DIAG_LD + jj] = xjj;
-    if (jj > 0)
-      for (int r = tid; r < TB; r += NT) nxt[r] = r >= jj ? A[r * DIAG_LD + (jj - 1)] : TA(0);
-    __syncthreads();
   }
   __syncthreads();
+  // ---- inverse, block columns right to left
+  for (int jb = DNB - 2; jb >= 0; --jb) {
+    const int nb = DNB - 1 - jb;
+    for (int e = tid; e < nb * DB * DB; e += NT) {
+      const int q = e / (DB * DB), rem = e - q * (DB * DB), i = rem / DB, jc = rem - i * DB;
+      const int ib = jb + 1 + q;
+      TA sacc = TA(0);
+      for (int kb2 = jb + 1; kb2 <= ib; ++kb2) {
+        const TA* xr = A + (ib * DB + i) * DIAG_LD + kb2 * DB;
+        const TA* lc = A + (kb2 * DB) * DIAG_LD + jb * DB + jc;
+#pragma unroll 8
+        for (int kk = 0; kk < DB; ++kk) sacc += xr[kk] * lc[kk * DIAG_LD];
+      }
+      Tt[(q * DB + i) * DT_LD + jc] = sacc;
+    }
+    __syncthreads();
+    for (int e = tid; e < nb * DB * DB; e += NT) {
+      const int q = e / (DB * DB), rem = e - q * (DB * DB), i = rem / DB, jc = rem - i * DB;
+      const int ib = jb + 1 + q;
+      TA sacc = TA(0);
+      for (int kk = jc; kk < DB; ++kk) sacc += Tt[(q * DB + i) * DT_LD + kk] * A[(jb * DB + kk) * DIAG_LD + jb * DB + jc];
+      A[(ib * DB + i) * DIAG_LD + jb * DB + jc] = -sacc;
+    }
+    __syncthreads();
+  }
   T* inv = a.invdiag + pd.invdiag_off + (int64_t)a.j * TB * TB;
   for (int idx = tid; idx < TB * TB; idx += NT) {
     const int r = idx >> 7, c = idx & (TB - 1);
@@ -376,7 +510,7 @@ static inline int pad8(int n) { return ((n + 7) / 8) * 8; }
 
 template <typename T>
 size_t diag_lds_bytes() {
-  return sizeof(T) * (size_t)(TB * DIAG_LD + 4 * TB);
+  return sizeof(T) * (size_t)(TB * DIAG_LD + (DNB - 1) * DB * DT_LD);
 }
 
 template <typename T>
