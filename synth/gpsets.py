@@ -2,12 +2,13 @@
 
 Training sets: n = 4096 points uniform in [0,1]^d, d uniform in 1..8; held-out
 sets: n = 65536, d = 8.  Hyperparameters are drawn log-uniformly (per-input
-length-scales in [0.2, 2], signal variance in [0.5, 2], noise variance in
-[0.01, 0.1]); outputs are a random-Fourier-feature approximation of a draw
+length-scales in [0.05, 2], signal variance in [0.1, 10], noise variance in
+[1e-3, 0.5]); outputs are a random-Fourier-feature approximation of a draw
 from the zero-mean SE-ARD prior plus Gaussian noise, standardised to zero mean
 and unit variance (the network and the likelihood fits work in that scale).
-Blocks: sorted on the first input, 256 points each; support set: 256 random
-inputs; Markov order B = 2 (the same LMA model for training and held-out sets).
+Blocks: sorted on the first input, 256 points each for the training sets
+(M = 16), 1024 for the held-out sets (M = 64); support set: 256 random inputs;
+Markov order B = 2.
 
 Every set is identified by (kind, index) and drawn from its own seed, so any
 subset can be regenerated independently.  Inputs only: nothing here computes
@@ -17,9 +18,9 @@ import numpy as np
 
 from . import ROOT_SEED, Problem, _loguniform, rff_draw, sorted_partition
 
-ELL = (0.2, 2.0)
-SF2 = (0.5, 2.0)
-SN2 = (0.01, 0.1)
+ELL = (0.05, 2.0)
+SF2 = (0.1, 10.0)
+SN2 = (1e-3, 0.5)
 KIND = {"train": 1, "heldout": 2}
 
 
@@ -40,7 +41,7 @@ def gp_set(kind: str, index: int, n: int = None, d: int = None, s: int = None, b
         n = n or 65536
         d = d or 8
         s = s or 256
-        block = block or 256
+        block = block or 1024
     ell = _loguniform(r_h, *ELL, size=d)
     sf2 = float(_loguniform(r_h, *SF2))
     sn2 = float(_loguniform(r_h, *SN2))
