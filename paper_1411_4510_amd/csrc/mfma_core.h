@@ -178,6 +178,10 @@ __device__ __forceinline__ void wave_gemm_fold(fv4 (&acc)[4][4], const float* __
   wave_gemm_impl<float, float, true, PF, true>(acc, A, lda, anr, Bm, ldb, bnr, k0, k1, arow0, brow0, lane, fold);
 }
 
+// Accumulators start as the result of an MFMA of zero operands (exactly +0):
+// started from constant zeros, the compiler keeps the loop-carried accumulators
+// of a k loop in vector registers and copies all of them into the accumulation
+// registers and back on every iteration; an MFMA result stays in place.
 template <typename Tc>
 __device__ inline void zero_acc(typename Mfma<Tc>::acc (&acc)[4][4]) {
 #pragma unroll
