@@ -66,20 +66,29 @@ def algorithmic_flops(p):
     return float(f_fit), float(f_pred)
 
 
+def engine_source_hash():
+    """SHA-256 (first 16 hex digits) of the engine kernel sources without their
+    comment lines and blank lines: the code the traffic counters were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for fn in ("engine.hip", "engine.h", "mfma_core.h"):
+        with open(os.path.join(ROOT, "paper_1411_4510_amd", "csrc", fn)) as f:
+            for line in f:
+                t = line.strip()
+                if t and not t.startswith("//"):
+                    h.update(t.encode() + b"\n")
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel_mode):
     """HBM bytes per k_update launch from the committed PMC runs, if the kernel
     source has not changed since they were taken (else None)."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"k_update_{kernel_mode}_n524288_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    h = hashlib.sha256()
-    for fn in ("engine.hip", "engine.h", "mfma_core.h"):
-        with open(os.path.join(ROOT, "paper_1411_4510_amd", "csrc", fn), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest()[:16] != rec["source_sha256_16"]:
+    if engine_source_hash() != rec["source_sha256_16"]:
         return None
     return rec["hbm_bytes_per_launch"]
 
